@@ -1,0 +1,193 @@
+/*
+ * kvop — KV-cache-backed semantic operators on AMD MI355X (gfx950).
+ *
+ * C ABI of the library.  The operations follow the paper's description of its
+ * KV cache-enabled operators (Section 5):
+ *   - offline, every document is fed once through the decoder and its keys and
+ *     values are kept ("Offline: KV Cache Creation")            -> kvop_kv_build
+ *   - online, an operator appends its query (instruction suffix) to the cached
+ *     documents and one batched forward pass yields one output per item; a
+ *     filter reads the logits of the answer tokens, forms their log-odds and
+ *     accepts, rejects or marks the item unsure against two thresholds
+ *     (Section 5 "Online: Query Execution"; thresholds on log-odds as in
+ *     Section 4.1, Eq. 14 at zero temperature); a map decodes a longer output;
+ *     a join is a filter over pairs of the cartesian product (Section 4.2)
+ *                                                                -> kvop_op_eval
+ *   - query-agnostic compression keeps a fraction of each document's rows
+ *     (Section 2.3, Section 5); the kept rows are passed in as index lists.
+ *   - the learned proxy is the cheap first stage of a two-stage cascade: it
+ *     answers confident items and passes the rest on as unsure (cascade
+ *     semantics, Section 4.1 Eqs. 1-3)                           -> kvop_proxy_*
+ *
+ * Conventions for every call:
+ *   - "dev" pointers are device (HBM) pointers on the current HIP device,
+ *     "host" pointers are ordinary host memory.  All buffers are owned by the
+ *     caller unless stated otherwise; the library never frees them.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Work is enqueued on it asynchronously unless a call says it synchronises.
+ *   - Errors: every call returns a kvop_status.  No C++ exception crosses the
+ *     ABI.  On an argument error (EINVAL, EBADHANDLE, ENOMEM) nothing has been
+ *     enqueued and outputs are untouched.  kvop_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - Not thread-safe per object: calls on one model/pool from several host
+ *     threads must be serialised by the caller.
+ */
+#ifndef KVOP_H
+#define KVOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum kvop_status {
+  KVOP_OK = 0,
+  KVOP_EINVAL = 1,      /* invalid argument, shape or index list */
+  KVOP_ENOMEM = 2,      /* device memory or cache pool exhausted */
+  KVOP_EBADHANDLE = 3,  /* released, foreign or corrupt cache handle */
+  KVOP_EDEVICE = 4      /* a HIP runtime error (also asynchronous faults seen later) */
+} kvop_status;
+
+/* Arithmetic of weights and activations.  Accumulation, softmax statistics,
+ * RMSNorm statistics and the logit-head reduction are FP32 in both. */
+typedef enum kvop_dtype { KVOP_F32 = 0, KVOP_BF16 = 1 } kvop_dtype;
+
+/* Storage of cached keys/values.  FP8 is OCP E4M3 (fn) with one FP32 scale per
+ * block of 16 rows of one (layer, kv head, K or V): scale = amax/448. */
+typedef enum kvop_kv_dtype { KVOP_KV_F32 = 0, KVOP_KV_BF16 = 1, KVOP_KV_FP8 = 2 } kvop_kv_dtype;
+
+typedef enum kvop_op_kind { KVOP_FILTER = 0, KVOP_MAP = 1, KVOP_JOIN = 2 } kvop_op_kind;
+
+/* Decoder shape: Llama-style pre-norm decoder, RMSNorm, rotary embedding
+ * (rotate-half pairs (i, i + head_dim/2), angle pos * rope_theta^(-2i/head_dim)),
+ * grouped-query attention (query head h uses kv head h / (n_heads/n_kv_heads)),
+ * SwiGLU feed-forward W_down(silu(W_gate x) * W_up x), final RMSNorm, untied head. */
+typedef struct kvop_model_cfg {
+  int32_t n_layers, d_model, n_heads, n_kv_heads, head_dim, d_ffn, vocab;
+  float rms_eps, rope_theta;
+} kvop_model_cfg;
+
+typedef struct kvop_model kvop_model;
+typedef struct kvop_pool kvop_pool;
+typedef struct kvop_proxy kvop_proxy;
+typedef uint64_t kvop_handle;
+
+/* Human-readable description of the last error on this thread ("" if none). */
+const char* kvop_last_error(void);
+
+/* Number of FP32 elements kvop_model_create expects for this shape. */
+int64_t kvop_weights_numel(const kvop_model_cfg* cfg);
+
+/* Create a model from FP32 master weights packed in one device buffer, in this
+ * order (row-major, linear maps stored [out, in] and applied as x W^T):
+ *   for each layer: attn_norm[d], wq[H*D, d], wk[Hkv*D, d], wv[Hkv*D, d],
+ *                   wo[d, H*D], ffn_norm[d], w_gate[F, d], w_up[F, d], w_down[d, F]
+ *   then final_norm[d], embed[V, d], head[V, d].
+ * The library converts/repacks them into its own buffers in `compute` dtype
+ * (norm gains stay FP32); the caller may free `weights_dev` after the call
+ * returns (the call synchronises `stream`).
+ * Errors: EINVAL on a bad shape (head_dim not 32/64/128, n_heads not a multiple
+ * of n_kv_heads, d_model/d_ffn not multiples of 64, n_weights mismatch);
+ * ENOMEM; EDEVICE. */
+kvop_status kvop_model_create(const kvop_model_cfg* cfg, const float* weights_dev, int64_t n_weights,
+                              kvop_dtype compute, void* stream, kvop_model** out);
+kvop_status kvop_model_destroy(kvop_model* model);
+
+/* A cache pool: `bytes` of device memory holding documents' caches in
+ * `kv_dtype`.  Each document occupies one contiguous region laid out
+ * [layer][kv head][K,V][row][head_dim] followed, for FP8, by its FP32 block
+ * scales [layer][kv head][K,V][ceil(L/16)].  The pool owns its memory. */
+kvop_status kvop_pool_create(kvop_model* model, kvop_kv_dtype kv_dtype, uint64_t bytes, kvop_pool** out);
+kvop_status kvop_pool_destroy(kvop_pool* pool);
+/* Bytes one document of length L occupies in this pool (rounded to 256). */
+uint64_t kvop_doc_bytes(const kvop_pool* pool, int64_t L);
+kvop_status kvop_pool_stats(const kvop_pool* pool, uint64_t* used_bytes, uint64_t* capacity_bytes,
+                            int32_t* live_docs);
+
+/* Offline cache creation (Section 5, "Offline"): prefill n_docs documents
+ * causally at positions 0..L-1 and keep every layer's rotated keys and values.
+ *   tokens_dev   : int32 token ids of all documents concatenated (device)
+ *   offsets_host : int64[n_docs+1], document i is tokens[offsets[i]:offsets[i+1]]
+ *   handles_out  : host array of n_docs handles, written on success
+ *   pooled_dev   : optional FP32 [n_docs, d_model] output (NULL to skip): the mean
+ *                  over the document's rows of the final-normed hidden state
+ *                  (the learned proxy's input feature)
+ * Errors: EINVAL (n_docs < 0, empty document, decreasing offsets); ENOMEM when the
+ * pool cannot hold all documents (then no handle is created); token ids are not
+ * range-checked on the host: ids outside [0, vocab) are clamped on the device. */
+kvop_status kvop_kv_build(kvop_pool* pool, const int32_t* tokens_dev, const int64_t* offsets_host,
+                          int32_t n_docs, void* stream, kvop_handle* handles_out, float* pooled_dev);
+
+/* Release documents' caches; their handles become invalid.  EBADHANDLE if any
+ * handle is not live in this pool (then nothing is released). */
+kvop_status kvop_kv_release(kvop_pool* pool, const kvop_handle* handles, int32_t n);
+
+/* Operator descriptor (read during the call only). */
+typedef struct kvop_op {
+  int32_t kind;               /* kvop_op_kind */
+  const int32_t* suffix_host; /* the operator's instruction suffix: token ids (host) */
+  int32_t suffix_len;         /* S >= 1 */
+  int32_t yes_id, no_id;      /* filter/join answer tokens ('1' and '0') */
+  float theta_pos, theta_neg; /* accept iff LO > theta_pos, reject iff LO < theta_neg */
+  int32_t label_lo, label_n;  /* map: decode over ids [label_lo, label_lo + label_n) */
+  int32_t n_gen;              /* map: number of ids to decode (>= 1) */
+  uint32_t flags;             /* KVOP_FLAG_* */
+} kvop_op;
+
+/* Skip the check that each list holds exactly k(r, L) rows (the caller may then
+ * pass any valid sorted list; r is only range-checked). */
+#define KVOP_FLAG_ANY_COUNT 1u
+
+/* Online execution (Section 5, "Online"): evaluate one operator over n_items
+ * items.  A filter/map item is one document; a join item is an ordered pair of
+ * documents (A, B) using handles[2i], handles[2i+1] and index lists 2i, 2i+1.
+ *   r               : retention in (0, 1]; each list must hold exactly
+ *                     k(r, L) = clamp(floor((round(1000 r) L + 500)/1000), min(4, L), L)
+ *                     rows unless KVOP_FLAG_ANY_COUNT
+ *   idx_dev         : int32 retained row indices of all lists concatenated (device);
+ *                     every list strictly increasing within [0, L)
+ *   idx_offsets_host: int64[n_lists+1] (n_lists = n_items, or 2 n_items for joins)
+ *   handles_host    : n_lists handles
+ *   logits_out_dev  : FP32 — filter/join: [n_items, 2] (yes, no);
+ *                     map: [n_items, n_gen, label_n] logits over the label slice
+ *   decision_out_dev: int8 [n_items] — 1 accept, 0 reject, -1 unsure (filter/join);
+ *                     may be NULL for a map
+ *   tokens_out_dev  : int32 [n_items, n_gen] decoded ids (map only, else NULL)
+ * The suffix is placed after the document's original length (positions L + j;
+ * for a join, B's rows sit at L_A + p and the suffix at L_A + L_B + j), sees every
+ * retained row and the earlier suffix rows.  The call synchronises `stream` once
+ * to validate the index lists before enqueuing any compute; the results are then
+ * produced asynchronously on `stream`.
+ * Errors: EINVAL (r out of range, wrong list count, unsorted or out-of-range
+ * index, bad op fields), EBADHANDLE, ENOMEM, EDEVICE. */
+kvop_status kvop_op_eval(kvop_pool* pool, const kvop_op* op, float r, const int32_t* idx_dev,
+                         const int64_t* idx_offsets_host, const kvop_handle* handles_host, int32_t n_items,
+                         void* stream, float* logits_out_dev, int8_t* decision_out_dev,
+                         int32_t* tokens_out_dev);
+
+/* ---- diagnostics and tuning ------------------------------------------------
+ * Run one projection C = A B^T with an explicit tile configuration `tile`
+ * (0 .. kvop_gemm_num_tiles(dtype)-1).  dtype: KVOP_F32 or KVOP_BF16 operands;
+ * epilogue 0 = store C in out_dtype, 1 = FP32 C += A B^T, 2 = SwiGLU over 16-row
+ * interleaved gate/up rows of B (C has N/2 columns).  Device pointers; strides in
+ * elements.  EINVAL when the tile cannot run the shape (K, lda, ldb must be
+ * multiples of 16 bytes / element size). */
+int32_t kvop_gemm_num_tiles(int32_t dtype);
+const char* kvop_gemm_tile_name(int32_t dtype, int32_t tile);
+kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epilogue, int32_t tile, const void* A,
+                            const void* B, void* Cm, int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb,
+                            int64_t ldc, void* stream);
+/* Record the best tile for (dtype, epilogue, N, K, M) in the library's tuning table
+ * (used by later kvop_kv_build / kvop_op_eval calls). */
+kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epilogue, int32_t N, int32_t K, int32_t M, int32_t tile);
+/* Copy the cached keys (kv = 0) or values (kv = 1) of one document, one layer and one
+ * kv head into out_dev as FP32 [L, head_dim] (FP8 entries decoded and scaled). */
+kvop_status kvop_debug_read_cache(kvop_pool* pool, kvop_handle handle, int32_t layer, int32_t kv_head, int32_t kv,
+                                  float* out_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KVOP_H */

@@ -1,0 +1,1047 @@
+// Host side of the C ABI: model weights, the cache pool (a first-fit allocator of
+// contiguous per-document regions with generation-tagged handles), the offline prefill
+// (kv_build) and the online operator evaluation (op_eval) for filter, map and join.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kvop.h"
+#include "kernels.h"
+
+using namespace kvop;
+
+namespace {
+
+thread_local std::string g_err;
+
+kvop_status fail(kvop_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPTRY(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(KVOP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr int kRopeMaxPos = 65536;
+constexpr int64_t kAlign = 256;
+
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Device buffer that grows on demand (synchronising the stream before a reallocation).
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t reserve(size_t bytes, hipStream_t st) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return e;
+      (void)hipFree(p);
+      p = nullptr;
+      cap = 0;
+    }
+    size_t want = std::max(bytes, cap + cap / 2);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) { p = nullptr; return e; }
+      want = bytes;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+  ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+// Pinned host staging with an event guarding its reuse.
+struct HostStage {
+  char* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  hipError_t reserve(size_t bytes) {
+    if (pending) {
+      hipError_t e = hipEventSynchronize(ev);
+      if (e != hipSuccess) return e;
+      pending = false;
+    }
+    if (!ev) {
+      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    if (bytes <= cap) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    size_t want = std::max(bytes, cap * 2);
+    hipError_t e = hipHostMalloc((void**)&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) { p = nullptr; cap = 0; return e; }
+    cap = want;
+    return hipSuccess;
+  }
+  ~HostStage() {
+    if (ev) { (void)hipEventSynchronize(ev); (void)hipEventDestroy(ev); }
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// Bump layout of one host staging area mirrored into one device area.
+struct Mirror {
+  std::vector<size_t> offs;
+  size_t size = 0;
+  size_t add(size_t bytes) {
+    size_t o = size;
+    size = align_up(size + bytes, 64);
+    offs.push_back(o);
+    return o;
+  }
+};
+
+}  // namespace
+
+// ================================================================== model
+struct kvop_model {
+  kvop_model_cfg cfg;
+  int dt;
+  struct Layer {
+    float* attn_norm;
+    float* ffn_norm;
+    void* wqkv;
+    void* wo;
+    void* wgu;
+    void* wdown;
+  };
+  std::vector<Layer> layers;
+  void* embed = nullptr;
+  void* head = nullptr;
+  float* final_norm = nullptr;
+  float* cos_tab = nullptr;
+  float* sin_tab = nullptr;
+  std::vector<void*> allocs;
+  // workspaces shared by kv_build and op_eval (calls on one model are serialised)
+  DevBuf ws;
+  DevBuf meta;
+  HostStage stage;
+  int* dflag = nullptr;
+  int* hflag = nullptr;
+
+  int qkv_cols() const { return (cfg.n_heads + 2 * cfg.n_kv_heads) * cfg.head_dim; }
+  int esz() const { return dt == DT_F32 ? 4 : 2; }
+  ~kvop_model() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (dflag) (void)hipFree(dflag);
+    if (hflag) (void)hipHostFree(hflag);
+  }
+};
+
+struct DocSlot {
+  uint64_t off = 0, bytes = 0;
+  int32_t L = 0;
+  uint32_t gen = 0;
+  bool live = false;
+};
+
+struct kvop_pool {
+  kvop_model* m;
+  int kvdt;
+  uint8_t* base = nullptr;
+  uint64_t cap = 0, used = 0;
+  uint32_t id;
+  std::map<uint64_t, uint64_t> free_list;  // offset -> size
+  std::vector<DocSlot> slots;
+  std::vector<uint32_t> free_slots;
+  int live = 0;
+};
+
+namespace {
+
+std::atomic<uint32_t> g_pool_ids{1};
+
+int kv_esz(int kvdt) { return kvdt == DT_F32 ? 4 : (kvdt == DT_BF16 ? 2 : 1); }
+
+uint64_t doc_bytes(const kvop_pool* p, int64_t L) {
+  const kvop_model_cfg& c = p->m->cfg;
+  int64_t elems = 2LL * c.n_layers * c.n_kv_heads * L * c.head_dim;
+  int64_t b = elems * kv_esz(p->kvdt);
+  if (p->kvdt == DT_FP8) b += 2LL * c.n_layers * c.n_kv_heads * ((L + 15) / 16) * 4;
+  return (uint64_t)align_up(b, kAlign);
+}
+
+bool pool_alloc(kvop_pool* p, uint64_t bytes, uint64_t* off) {
+  for (auto it = p->free_list.begin(); it != p->free_list.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      uint64_t rest = it->second - bytes, noff = it->first + bytes;
+      p->free_list.erase(it);
+      if (rest) p->free_list[noff] = rest;
+      p->used += bytes;
+      return true;
+    }
+  }
+  return false;
+}
+
+void pool_free(kvop_pool* p, uint64_t off, uint64_t bytes) {
+  p->used -= bytes;
+  auto it = p->free_list.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != p->free_list.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    p->free_list.erase(nx);
+  }
+  if (it != p->free_list.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      p->free_list.erase(it);
+    }
+  }
+}
+
+kvop_handle make_handle(const kvop_pool* p, uint32_t slot, uint32_t gen) {
+  return ((uint64_t)(p->id & 0xffff) << 48) | ((uint64_t)(gen & 0xffff) << 32) | slot;
+}
+
+const DocSlot* lookup(const kvop_pool* p, kvop_handle h) {
+  uint32_t pid = (uint32_t)(h >> 48), gen = (uint32_t)((h >> 32) & 0xffff), slot = (uint32_t)(h & 0xffffffffu);
+  if (pid != (p->id & 0xffff) || slot >= p->slots.size()) return nullptr;
+  const DocSlot& s = p->slots[slot];
+  if (!s.live || (s.gen & 0xffff) != gen) return nullptr;
+  return &s;
+}
+
+int64_t retained_count(float r, int64_t L) {
+  int64_t rm = (int64_t)std::llround((double)r * 1000.0);
+  int64_t k = (rm * L + 500) / 1000;
+  return std::min(std::max(k, std::min<int64_t>(4, L)), L);
+}
+
+struct LayerBufs {
+  float* x;
+  void* h;
+  void* qkv;
+  void* qalt;
+  void* attn;
+  void* act;
+};
+
+// Plan of one decoder layer over `rows` activation rows.  Only the rows
+// r*sel_stride + sel_off (r < n_sel) continue past the attention (the K/V of every row are
+// still produced): the last layer of op_eval continues with the last suffix row only.
+struct LayerPlan {
+  int rows;
+  const int32_t* pos;
+  const int32_t* alt_shift;  // joins: q_alt rotation shift per row (-1: none); may be null
+  AttnArgs attn;             // work list etc. (q/out/own filled by run_layer)
+  bool own_from_qkv;         // own keys are the rows of this pass
+  const void* own;           // otherwise: explicit own buffer
+  int64_t own_stride;
+  int own_kcol, own_vcol;
+  int n_sel, sel_stride, sel_off;  // rows continuing after attention (n_sel == rows: all)
+};
+
+// skip_tail: stop once this layer's keys/values exist (prefill's last layer when the final
+// hidden states are not needed)
+kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, uint8_t* pool, int kvdt,
+                      const KvBlock* kvblocks, int n_kvblocks, hipStream_t st, bool skip_tail = false) {
+  const kvop_model_cfg& c = m->cfg;
+  const kvop_model::Layer& W = m->layers[l];
+  const int d = c.d_model, H = c.n_heads, Hkv = c.n_kv_heads, D = c.head_dim, F = c.d_ffn;
+  const int qc = m->qkv_cols();
+  const int rows = lp.rows;
+  const int dt = m->dt;
+  HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, rows, d, c.rms_eps, b.h, d, st));
+  {
+    GemmShape s{rows, qc, d, d, d, qc};
+    HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.qkv, s, st));
+  }
+  if (n_kvblocks > 0) {
+    // prefill: rotate queries here; keys are rotated by the cache writer
+    HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, 0, D, lp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
+    HIPTRY(rope_write_kv(dt, kvdt, b.qkv, qc, kvblocks, n_kvblocks, H, Hkv, D, l, c.n_layers, m->cos_tab, m->sin_tab,
+                         pool, st));
+  } else {
+    HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, Hkv, D, lp.pos, m->cos_tab, m->sin_tab, lp.alt_shift ? b.qalt : nullptr,
+                   lp.alt_shift, st));
+  }
+  if (skip_tail) return KVOP_OK;
+  AttnArgs a = lp.attn;
+  a.q = b.qkv;
+  a.q_alt = lp.alt_shift ? b.qalt : nullptr;
+  a.q_stride = qc;
+  if (lp.own_from_qkv) {
+    a.own = b.qkv;
+    a.own_stride = qc;
+    a.own_kcol = H * D;
+    a.own_vcol = (H + Hkv) * D;
+  } else {
+    a.own = lp.own;
+    a.own_stride = lp.own_stride;
+    a.own_kcol = lp.own_kcol;
+    a.own_vcol = lp.own_vcol;
+  }
+  a.out = b.attn;
+  a.out_stride = H * D;
+  a.layer = l;
+  a.n_layers = c.n_layers;
+  a.Hkv = Hkv;
+  a.G = H / Hkv;
+  a.pool = pool;
+  a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
+  HIPTRY(attention(dt, kvdt, D, a, st));
+  // rows continuing: all, or a strided selection (last row of each item)
+  const int n = lp.n_sel;
+  const int64_t sa = (int64_t)lp.sel_stride;
+  const char* attn_sel = (const char*)b.attn + (int64_t)lp.sel_off * H * D * m->esz();
+  float* x_sel = b.x + (int64_t)lp.sel_off * d;
+  {
+    GemmShape s{n, d, H * D, sa * H * D, H * D, sa * d};
+    HIPTRY(gemm(dt, DT_F32, EPI_ADD, gemm_pick_tile(dt, EPI_ADD, s), attn_sel, W.wo, x_sel, s, st));
+  }
+  HIPTRY(rmsnorm_rows(dt, x_sel, sa * d, W.ffn_norm, n, d, c.rms_eps, b.h, d, st));
+  {
+    GemmShape s{n, 2 * F, d, d, d, F};
+    HIPTRY(gemm(dt, dt, EPI_SWIGLU, gemm_pick_tile(dt, EPI_SWIGLU, s), b.h, W.wgu, b.act, s, st));
+  }
+  {
+    GemmShape s{n, d, F, F, F, sa * d};
+    HIPTRY(gemm(dt, DT_F32, EPI_ADD, gemm_pick_tile(dt, EPI_ADD, s), b.act, W.wdown, x_sel, s, st));
+  }
+  return KVOP_OK;
+}
+
+size_t act_bytes(const kvop_model* m, int64_t rows, bool join) {
+  const kvop_model_cfg& c = m->cfg;
+  int e = m->esz();
+  size_t b = 0;
+  b += align_up(rows * c.d_model * 4, kAlign);                          // x
+  b += align_up(rows * c.d_model * e, kAlign);                          // h
+  b += align_up(rows * (int64_t)m->qkv_cols() * e, kAlign);             // qkv
+  b += join ? align_up(rows * (int64_t)m->qkv_cols() * e, kAlign) : 0;  // q_alt (qkv layout)
+  b += align_up(rows * (int64_t)c.n_heads * c.head_dim * e, kAlign);    // attn
+  b += align_up(rows * (int64_t)c.d_ffn * e, kAlign);                   // act
+  return b;
+}
+
+LayerBufs carve(kvop_model* m, char* base, int64_t rows, bool join) {
+  const kvop_model_cfg& c = m->cfg;
+  int e = m->esz();
+  LayerBufs b{};
+  char* p = base;
+  b.x = (float*)p; p += align_up(rows * c.d_model * 4, kAlign);
+  b.h = p; p += align_up(rows * c.d_model * e, kAlign);
+  b.qkv = p; p += align_up(rows * (int64_t)m->qkv_cols() * e, kAlign);
+  if (join) { b.qalt = p; p += align_up(rows * (int64_t)m->qkv_cols() * e, kAlign); }
+  b.attn = p; p += align_up(rows * (int64_t)c.n_heads * c.head_dim * e, kAlign);
+  b.act = p;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kvop_last_error(void) { return g_err.c_str(); }
+
+int64_t kvop_weights_numel(const kvop_model_cfg* c) {
+  if (!c) return -1;
+  int64_t d = c->d_model, hd = c->head_dim, F = c->d_ffn;
+  int64_t per = d + (int64_t)c->n_heads * hd * d + 2LL * c->n_kv_heads * hd * d + d * c->n_heads * hd + d +
+                3LL * F * d;
+  return per * c->n_layers + d + 2LL * c->vocab * d;
+}
+
+kvop_status kvop_model_create(const kvop_model_cfg* cfg, const float* w, int64_t n_weights, kvop_dtype compute,
+                              void* stream, kvop_model** out) {
+  if (!cfg || !w || !out) return fail(KVOP_EINVAL, "null argument");
+  const kvop_model_cfg c = *cfg;
+  if (c.n_layers < 1 || c.n_heads < 1 || c.n_kv_heads < 1 || c.n_heads % c.n_kv_heads)
+    return fail(KVOP_EINVAL, "bad head configuration");
+  if (c.head_dim != 32 && c.head_dim != 64 && c.head_dim != 128) return fail(KVOP_EINVAL, "head_dim must be 32/64/128");
+  if (c.d_model % 64 || c.d_ffn % 64 || c.vocab < 2) return fail(KVOP_EINVAL, "d_model and d_ffn must be multiples of 64");
+  if ((c.n_heads / c.n_kv_heads) > 64) return fail(KVOP_EINVAL, "group too large");
+  if (compute != KVOP_F32 && compute != KVOP_BF16) return fail(KVOP_EINVAL, "bad compute dtype");
+  if (n_weights != kvop_weights_numel(cfg)) return fail(KVOP_EINVAL, "weight count mismatch");
+  hipStream_t st = (hipStream_t)stream;
+  kvop_model* m = new (std::nothrow) kvop_model();
+  if (!m) return fail(KVOP_ENOMEM, "host allocation");
+  m->cfg = c;
+  m->dt = compute == KVOP_F32 ? DT_F32 : DT_BF16;
+  const int64_t d = c.d_model, H = c.n_heads, Hkv = c.n_kv_heads, D = c.head_dim, F = c.d_ffn, V = c.vocab;
+  const int e = m->esz();
+  auto dalloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    m->allocs.push_back(p);
+    return p;
+  };
+  kvop_status st_ok = KVOP_OK;
+  auto conv = [&](const float* src, const float* src2, int64_t rows, int64_t cols, void* dst, int inter) {
+    if (st_ok == KVOP_OK && convert_weights(m->dt, src, src2, rows, cols, dst, inter, st) != hipSuccess)
+      st_ok = fail(KVOP_EDEVICE, "weight conversion launch failed");
+  };
+  const float* p = w;
+  for (int l = 0; l < c.n_layers; l++) {
+    kvop_model::Layer L{};
+    L.attn_norm = (float*)dalloc(d * 4);
+    L.ffn_norm = (float*)dalloc(d * 4);
+    L.wqkv = dalloc((H + 2 * Hkv) * D * d * e);
+    L.wo = dalloc(d * H * D * e);
+    L.wgu = dalloc(2 * F * d * e);
+    L.wdown = dalloc(d * F * e);
+    if (!L.attn_norm || !L.ffn_norm || !L.wqkv || !L.wo || !L.wgu || !L.wdown) {
+      delete m;
+      return fail(KVOP_ENOMEM, "weight allocation");
+    }
+    if (hipMemcpyAsync(L.attn_norm, p, d * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) st_ok = KVOP_EDEVICE;
+    p += d;
+    conv(p, nullptr, H * D, d, L.wqkv, 0);
+    p += H * D * d;
+    conv(p, nullptr, Hkv * D, d, (char*)L.wqkv + H * D * d * e, 0);
+    p += Hkv * D * d;
+    conv(p, nullptr, Hkv * D, d, (char*)L.wqkv + (H + Hkv) * D * d * e, 0);
+    p += Hkv * D * d;
+    conv(p, nullptr, d, H * D, L.wo, 0);
+    p += d * H * D;
+    if (hipMemcpyAsync(L.ffn_norm, p, d * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) st_ok = KVOP_EDEVICE;
+    p += d;
+    conv(p, p + F * d, F, d, L.wgu, 1);
+    p += 2 * F * d;
+    conv(p, nullptr, d, F, L.wdown, 0);
+    p += d * F;
+    m->layers.push_back(L);
+  }
+  m->final_norm = (float*)dalloc(d * 4);
+  m->embed = dalloc(V * d * e);
+  m->head = dalloc(V * d * e);
+  if (!m->final_norm || !m->embed || !m->head) {
+    delete m;
+    return fail(KVOP_ENOMEM, "weight allocation");
+  }
+  if (hipMemcpyAsync(m->final_norm, p, d * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) st_ok = KVOP_EDEVICE;
+  p += d;
+  conv(p, nullptr, V, d, m->embed, 0);
+  p += V * d;
+  conv(p, nullptr, V, d, m->head, 0);
+  // rotary tables, evaluated in double precision: angle(pos, i) = pos * theta^(-2i/D)
+  {
+    const int half = (int)D / 2;
+    std::vector<float> ct((size_t)kRopeMaxPos * half), sn((size_t)kRopeMaxPos * half);
+    for (int i = 0; i < half; i++) {
+      double inv = std::pow((double)c.rope_theta, -2.0 * i / (double)D);
+      for (int ps = 0; ps < kRopeMaxPos; ps++) {
+        double a = (double)ps * inv;
+        ct[(size_t)ps * half + i] = (float)std::cos(a);
+        sn[(size_t)ps * half + i] = (float)std::sin(a);
+      }
+    }
+    m->cos_tab = (float*)dalloc(ct.size() * 4);
+    m->sin_tab = (float*)dalloc(sn.size() * 4);
+    if (!m->cos_tab || !m->sin_tab) {
+      delete m;
+      return fail(KVOP_ENOMEM, "rope table allocation");
+    }
+    if (hipMemcpyAsync(m->cos_tab, ct.data(), ct.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) st_ok = KVOP_EDEVICE;
+    if (hipMemcpyAsync(m->sin_tab, sn.data(), sn.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) st_ok = KVOP_EDEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) st_ok = KVOP_EDEVICE;
+  }
+  if (hipMalloc((void**)&m->dflag, 64) != hipSuccess || hipHostMalloc((void**)&m->hflag, 64, 0) != hipSuccess) {
+    delete m;
+    return fail(KVOP_ENOMEM, "flag allocation");
+  }
+  if (st_ok != KVOP_OK) {
+    delete m;
+    return fail(KVOP_EDEVICE, g_err.empty() ? "model upload failed" : g_err);
+  }
+  *out = m;
+  return KVOP_OK;
+}
+
+kvop_status kvop_model_destroy(kvop_model* m) {
+  if (!m) return fail(KVOP_EINVAL, "null model");
+  (void)hipDeviceSynchronize();
+  delete m;
+  return KVOP_OK;
+}
+
+kvop_status kvop_pool_create(kvop_model* m, kvop_kv_dtype kvd, uint64_t bytes, kvop_pool** out) {
+  if (!m || !out) return fail(KVOP_EINVAL, "null argument");
+  int kvdt = kvd == KVOP_KV_F32 ? DT_F32 : (kvd == KVOP_KV_BF16 ? DT_BF16 : (kvd == KVOP_KV_FP8 ? DT_FP8 : -1));
+  if (kvdt < 0) return fail(KVOP_EINVAL, "bad kv dtype");
+  if (m->dt == DT_F32 && kvdt != DT_F32) return fail(KVOP_EINVAL, "an FP32 model keeps an FP32 cache");
+  if (m->dt == DT_BF16 && kvdt == DT_F32) return fail(KVOP_EINVAL, "a BF16 model keeps a BF16 or FP8 cache");
+  bytes = (uint64_t)align_up((int64_t)bytes, kAlign);
+  if (bytes == 0) return fail(KVOP_EINVAL, "empty pool");
+  kvop_pool* p = new (std::nothrow) kvop_pool();
+  if (!p) return fail(KVOP_ENOMEM, "host allocation");
+  p->m = m;
+  p->kvdt = kvdt;
+  p->cap = bytes;
+  p->id = g_pool_ids.fetch_add(1);
+  if (hipMalloc((void**)&p->base, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return fail(KVOP_ENOMEM, "pool allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  p->free_list[0] = bytes;
+  *out = p;
+  return KVOP_OK;
+}
+
+kvop_status kvop_pool_destroy(kvop_pool* p) {
+  if (!p) return fail(KVOP_EINVAL, "null pool");
+  (void)hipDeviceSynchronize();
+  (void)hipFree(p->base);
+  delete p;
+  return KVOP_OK;
+}
+
+uint64_t kvop_doc_bytes(const kvop_pool* p, int64_t L) { return p && L > 0 ? doc_bytes(p, L) : 0; }
+
+kvop_status kvop_pool_stats(const kvop_pool* p, uint64_t* used, uint64_t* cap, int32_t* live) {
+  if (!p) return fail(KVOP_EINVAL, "null pool");
+  if (used) *used = p->used;
+  if (cap) *cap = p->cap;
+  if (live) *live = p->live;
+  return KVOP_OK;
+}
+
+kvop_status kvop_kv_release(kvop_pool* p, const kvop_handle* hs, int32_t n) {
+  if (!p || (n > 0 && !hs) || n < 0) return fail(KVOP_EINVAL, "bad arguments");
+  std::vector<uint32_t> slots;
+  for (int i = 0; i < n; i++) {
+    if (!lookup(p, hs[i])) return fail(KVOP_EBADHANDLE, "handle " + std::to_string(i) + " is not live in this pool");
+    uint32_t s = (uint32_t)(hs[i] & 0xffffffffu);
+    if (std::find(slots.begin(), slots.end(), s) != slots.end())
+      return fail(KVOP_EBADHANDLE, "handle released twice in one call");
+    slots.push_back(s);
+  }
+  for (uint32_t s : slots) {
+    DocSlot& d = p->slots[s];
+    pool_free(p, d.off, d.bytes);
+    d.live = false;
+    d.gen++;
+    p->free_slots.push_back(s);
+    p->live--;
+  }
+  return KVOP_OK;
+}
+
+// ------------------------------------------------------------------ kv_build
+kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* offsets, int32_t n, void* stream,
+                          kvop_handle* handles_out, float* pooled) {
+  if (!p || n < 0 || (n > 0 && (!tokens || !offsets || !handles_out))) return fail(KVOP_EINVAL, "bad arguments");
+  if (n == 0) return KVOP_OK;
+  kvop_model* m = p->m;
+  const kvop_model_cfg& c = m->cfg;
+  hipStream_t st = (hipStream_t)stream;
+  for (int i = 0; i < n; i++) {
+    int64_t L = offsets[i + 1] - offsets[i];
+    if (L < 1) return fail(KVOP_EINVAL, "document " + std::to_string(i) + " is empty or offsets decrease");
+    if (L >= kRopeMaxPos) return fail(KVOP_EINVAL, "document longer than the rotary table");
+  }
+  // allocate every region first (all or nothing)
+  std::vector<uint64_t> offs(n), sizes(n);
+  for (int i = 0; i < n; i++) {
+    sizes[i] = doc_bytes(p, offsets[i + 1] - offsets[i]);
+    if (!pool_alloc(p, sizes[i], &offs[i])) {
+      for (int j = 0; j < i; j++) pool_free(p, offs[j], sizes[j]);
+      return fail(KVOP_ENOMEM, "cache pool full after " + std::to_string(i) + " of " + std::to_string(n) + " documents");
+    }
+  }
+  auto rollback = [&]() { for (int j = 0; j < n; j++) pool_free(p, offs[j], sizes[j]); };
+
+  const int d = c.d_model, H = c.n_heads, Hkv = c.n_kv_heads, D = c.head_dim, G = H / Hkv;
+  const int Pmax = std::max(1, std::min(64 / G, 64));
+  const int64_t chunk_rows = 65536;
+  int i0 = 0;
+  while (i0 < n) {
+    // documents [i0, i1) in this chunk
+    int i1 = i0;
+    int64_t rows = 0;
+    while (i1 < n && (i1 == i0 || rows + (offsets[i1 + 1] - offsets[i1]) <= chunk_rows)) {
+      rows += offsets[i1 + 1] - offsets[i1];
+      i1++;
+    }
+    const int nd = i1 - i0;
+    // host-built metadata
+    std::vector<int32_t> pos(rows);
+    std::vector<KvBlock> blocks;
+    std::vector<AttnWork> work;
+    std::vector<int64_t> row_off(nd + 1);
+    int64_t r = 0;
+    for (int i = i0; i < i1; i++) {
+      int L = (int)(offsets[i + 1] - offsets[i]);
+      row_off[i - i0] = r;
+      for (int q = 0; q < L; q++) pos[r + q] = q;
+      for (int p0 = 0; p0 < L; p0 += 16) blocks.push_back(KvBlock{(int64_t)offs[i], L, p0, (int32_t)(r + p0), 0});
+      for (int p0 = 0; p0 < L; p0 += Pmax) {
+        AttnWork w{};
+        w.off_a = (int64_t)offs[i];
+        w.off_b = -1;
+        w.idx_a = -1;
+        w.idx_b = -1;
+        w.L_a = L;
+        w.n_a = std::min(L, p0 + Pmax);
+        w.q_row0 = (int32_t)(r + p0);
+        w.q_pos0 = p0;
+        w.n_q = std::min(Pmax, L - p0);
+        work.push_back(w);
+      }
+      r += L;
+    }
+    row_off[nd] = r;
+    // longest key ranges first
+    std::stable_sort(work.begin(), work.end(), [](const AttnWork& a, const AttnWork& b) { return a.n_a > b.n_a; });
+    Mirror mir;
+    size_t o_pos = mir.add(pos.size() * 4), o_blk = mir.add(blocks.size() * sizeof(KvBlock)),
+           o_work = mir.add(work.size() * sizeof(AttnWork)), o_roff = mir.add(row_off.size() * 8),
+           o_inv = mir.add(rows * 4);
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess) {
+      rollback();
+      return fail(KVOP_ENOMEM, "metadata staging");
+    }
+    memcpy(m->stage.p + o_pos, pos.data(), pos.size() * 4);
+    memcpy(m->stage.p + o_blk, blocks.data(), blocks.size() * sizeof(KvBlock));
+    memcpy(m->stage.p + o_work, work.data(), work.size() * sizeof(AttnWork));
+    memcpy(m->stage.p + o_roff, row_off.data(), row_off.size() * 8);
+    char* md = (char*)m->meta.p;
+    if (hipMemcpyAsync(md, m->stage.p, o_inv, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(m->stage.ev, st) != hipSuccess) {
+      rollback();
+      return fail(KVOP_EDEVICE, "metadata upload");
+    }
+    m->stage.pending = true;
+    if (m->ws.reserve(act_bytes(m, rows, false), st) != hipSuccess) {
+      rollback();
+      return fail(KVOP_ENOMEM, "activation workspace for " + std::to_string(rows) + " rows");
+    }
+    LayerBufs b = carve(m, (char*)m->ws.p, rows, false);
+    if (embed_rows(m->dt, m->embed, tokens + offsets[i0], (int)rows, d, c.vocab, b.x, st) != hipSuccess) {
+      rollback();
+      return fail(KVOP_EDEVICE, "embedding launch");
+    }
+    LayerPlan lp{};
+    lp.rows = (int)rows;
+    lp.pos = (const int32_t*)(md + o_pos);
+    lp.alt_shift = nullptr;
+    lp.attn.work = (const AttnWork*)(md + o_work);
+    lp.attn.n_work = (int)work.size();
+    lp.attn.idx = nullptr;
+    lp.attn.Pmax = Pmax;
+    lp.own_from_qkv = false;
+    lp.own = nullptr;
+    lp.n_sel = (int)rows;
+    lp.sel_stride = 1;
+    lp.sel_off = 0;
+    for (int l = 0; l < c.n_layers; l++) {
+      bool tail = (l + 1 < c.n_layers) || pooled != nullptr;
+      kvop_status s = run_layer(m, l, b, lp, p->base, p->kvdt, (const KvBlock*)(md + o_blk), (int)blocks.size(), st,
+                                !tail);
+      if (s != KVOP_OK) {
+        rollback();
+        return s;
+      }
+    }
+    if (pooled) {
+      if (pooled_mean(b.x, d, (const int64_t*)(md + o_roff), nd, (int)rows, m->final_norm, c.rms_eps,
+                      (float*)(md + o_inv), pooled + (int64_t)i0 * d, st) != hipSuccess) {
+        rollback();
+        return fail(KVOP_EDEVICE, "pooled launch");
+      }
+    }
+    i0 = i1;
+  }
+  // publish handles
+  for (int i = 0; i < n; i++) {
+    uint32_t slot;
+    if (!p->free_slots.empty()) {
+      slot = p->free_slots.back();
+      p->free_slots.pop_back();
+    } else {
+      slot = (uint32_t)p->slots.size();
+      p->slots.push_back(DocSlot{});
+    }
+    DocSlot& s = p->slots[slot];
+    s.off = offs[i];
+    s.bytes = sizes[i];
+    s.L = (int32_t)(offsets[i + 1] - offsets[i]);
+    s.live = true;
+    handles_out[i] = make_handle(p, slot, s.gen);
+    p->live++;
+  }
+  return KVOP_OK;
+}
+
+// ------------------------------------------------------------------ op_eval
+kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
+                         const kvop_handle* hs, int32_t n_items, void* stream, float* logits, int8_t* decision,
+                         int32_t* tokens_out) {
+  if (!p || !op || n_items < 0) return fail(KVOP_EINVAL, "bad arguments");
+  if (n_items == 0) return KVOP_OK;
+  kvop_model* m = p->m;
+  const kvop_model_cfg& c = m->cfg;
+  hipStream_t st = (hipStream_t)stream;
+  const int kind = op->kind;
+  if (kind != KVOP_FILTER && kind != KVOP_MAP && kind != KVOP_JOIN) return fail(KVOP_EINVAL, "bad op kind");
+  if (!(r > 0.f && r <= 1.f)) return fail(KVOP_EINVAL, "retention must be in (0, 1]");
+  const int S = op->suffix_len;
+  if (S < 1 || !op->suffix_host) return fail(KVOP_EINVAL, "empty suffix");
+  if (!idx || !idx_off || !hs || !logits) return fail(KVOP_EINVAL, "null buffer");
+  for (int j = 0; j < S; j++)
+    if (op->suffix_host[j] < 0 || op->suffix_host[j] >= c.vocab) return fail(KVOP_EINVAL, "suffix id out of range");
+  int n_gen = 1;
+  if (kind == KVOP_MAP) {
+    n_gen = op->n_gen;
+    if (n_gen < 1 || op->label_n < 1 || op->label_lo < 0 || op->label_lo + op->label_n > c.vocab || !tokens_out)
+      return fail(KVOP_EINVAL, "bad map fields");
+  } else {
+    if (op->yes_id < 0 || op->yes_id >= c.vocab || op->no_id < 0 || op->no_id >= c.vocab)
+      return fail(KVOP_EINVAL, "bad answer ids");
+  }
+  const bool join = kind == KVOP_JOIN;
+  const int per = join ? 2 : 1;
+  const int n_lists = n_items * per;
+  std::vector<const DocSlot*> docs(n_lists);
+  std::vector<ListCheck> checks(n_lists);
+  for (int i = 0; i < n_lists; i++) {
+    docs[i] = lookup(p, hs[i]);
+    if (!docs[i]) return fail(KVOP_EBADHANDLE, "handle " + std::to_string(i) + " is not live in this pool");
+    int64_t k = idx_off[i + 1] - idx_off[i];
+    if (k < 1 || k > docs[i]->L) return fail(KVOP_EINVAL, "list " + std::to_string(i) + " has a bad length");
+    if (!(op->flags & KVOP_FLAG_ANY_COUNT) && k != retained_count(r, docs[i]->L))
+      return fail(KVOP_EINVAL, "list " + std::to_string(i) + " holds " + std::to_string(k) + " rows, k(r, L) = " +
+                                   std::to_string(retained_count(r, docs[i]->L)));
+    checks[i] = ListCheck{idx_off[i], (int32_t)k, docs[i]->L};
+  }
+  for (int i = 0; i < n_items; i++) {
+    int64_t top = join ? (int64_t)docs[2 * i]->L + docs[2 * i + 1]->L : docs[i]->L;
+    if (top + S + n_gen >= kRopeMaxPos) return fail(KVOP_EINVAL, "positions exceed the rotary table");
+  }
+  // device-side validation of the lists (sorted, in range), before any compute
+  {
+    Mirror mir;
+    size_t o_chk = mir.add(checks.size() * sizeof(ListCheck));
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+      return fail(KVOP_ENOMEM, "metadata staging");
+    memcpy(m->stage.p + o_chk, checks.data(), checks.size() * sizeof(ListCheck));
+    HIPTRY(hipMemcpyAsync(m->meta.p, m->stage.p, mir.size, hipMemcpyHostToDevice, st));
+    HIPTRY(hipMemsetAsync(m->dflag, 0, 4, st));
+    HIPTRY(validate_lists(idx, (const ListCheck*)m->meta.p, n_lists, m->dflag, st));
+    HIPTRY(hipMemcpyAsync(m->hflag, m->dflag, 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (m->hflag[0] != 0)
+      return fail(KVOP_EINVAL, std::to_string(m->hflag[0]) + " index list(s) unsorted or out of range");
+  }
+
+  const int d = c.d_model, H = c.n_heads, Hkv = c.n_kv_heads, D = c.head_dim, G = H / Hkv, F = c.d_ffn;
+  const int qc = m->qkv_cols();
+  const int Pmax_s = std::max(1, std::min(S, 64 / G));       // query positions per work item
+  const int wq = (S + Pmax_s - 1) / Pmax_s;                  // work items per operator item
+  const int64_t max_rows = 131072;
+  const int wave_items = (int)std::max<int64_t>(1, max_rows / S);
+  const int rows_per_item = S + (kind == KVOP_MAP ? n_gen - 1 : 0);  // own rows kept for decoding
+  const int e = m->esz();
+
+  for (int w0 = 0; w0 < n_items; w0 += wave_items) {
+    const int B = std::min(wave_items, n_items - w0);
+    const int64_t rows = (int64_t)B * S;
+    // per-row positions and (joins) rotation shifts; per-item work items
+    std::vector<int32_t> pos(rows), shift(join ? rows : 0);
+    std::vector<AttnWork> work;
+    work.reserve((size_t)B * wq);
+    std::vector<int32_t> pos_dec(kind == KVOP_MAP ? B : 0);
+    for (int b = 0; b < B; b++) {
+      int it = w0 + b;
+      const DocSlot* A = docs[it * per];
+      const DocSlot* Bd = join ? docs[it * per + 1] : nullptr;
+      int pos0 = A->L + (join ? Bd->L : 0);
+      for (int j = 0; j < S; j++) {
+        pos[(int64_t)b * S + j] = pos0 + j;
+        if (join) shift[(int64_t)b * S + j] = A->L;
+      }
+      for (int q0 = 0; q0 < S; q0 += Pmax_s) {
+        AttnWork w{};
+        w.off_a = (int64_t)A->off;
+        w.idx_a = idx_off[it * per];
+        w.L_a = A->L;
+        w.n_a = (int32_t)(idx_off[it * per + 1] - idx_off[it * per]);
+        if (join) {
+          w.off_b = (int64_t)Bd->off;
+          w.idx_b = idx_off[it * per + 1];
+          w.L_b = Bd->L;
+          w.n_b = (int32_t)(idx_off[it * per + 2] - idx_off[it * per + 1]);
+        } else {
+          w.off_b = -1;
+          w.idx_b = -1;
+        }
+        w.q_row0 = b * S + q0;
+        w.q_pos0 = pos0 + q0;
+        w.n_q = std::min(Pmax_s, S - q0);
+        w.own_row0 = b * S;
+        w.n_own = std::min(S, q0 + Pmax_s);
+        w.own_pos0 = pos0;
+        work.push_back(w);
+      }
+      if (kind == KVOP_MAP) pos_dec[b] = pos0 + S;
+    }
+    std::stable_sort(work.begin(), work.end(),
+                     [](const AttnWork& a, const AttnWork& b) { return a.n_a + a.n_b > b.n_a + b.n_b; });
+    // map decode: work items with one query position against (retained rows + own rows)
+    std::vector<AttnWork> dwork;
+    std::vector<int32_t> own_src, own_dst;
+    if (kind == KVOP_MAP) {
+      for (int b = 0; b < B; b++) {
+        int it = w0 + b;
+        const DocSlot* A = docs[it];
+        AttnWork w{};
+        w.off_a = (int64_t)A->off;
+        w.off_b = -1;
+        w.idx_a = idx_off[it];
+        w.idx_b = -1;
+        w.L_a = A->L;
+        w.n_a = (int32_t)(idx_off[it + 1] - idx_off[it]);
+        w.q_row0 = b;
+        w.n_q = 1;
+        w.own_row0 = b * rows_per_item;
+        w.own_pos0 = A->L;
+        dwork.push_back(w);
+      }
+      own_src.resize(rows);
+      own_dst.resize(rows);
+      for (int b = 0; b < B; b++)
+        for (int j = 0; j < S; j++) {
+          own_src[(int64_t)b * S + j] = b * S + j;
+          own_dst[(int64_t)b * S + j] = b * rows_per_item + j;
+        }
+    }
+    std::vector<int32_t> suffix(op->suffix_host, op->suffix_host + S);
+    Mirror mir;
+    size_t o_pos = mir.add(pos.size() * 4), o_shift = mir.add(shift.size() * 4),
+           o_work = mir.add(work.size() * sizeof(AttnWork)), o_suf = mir.add(S * 4),
+           o_dwork = mir.add(dwork.size() * sizeof(AttnWork)), o_os = mir.add(own_src.size() * 4),
+           o_od = mir.add(own_dst.size() * 4), o_pdec = mir.add(pos_dec.size() * 4),
+           o_ddst = mir.add(pos_dec.size() * 4), o_dsrc = mir.add(pos_dec.size() * 4),
+           o_ntok = mir.add(pos_dec.size() * 4);
+    // per-decode-step metadata, rewritten before each step (reserved now so that the device
+    // buffer never moves while the wave's metadata is in use)
+    size_t o_sp = mir.add(pos_dec.size() * 4), o_sd = mir.add(pos_dec.size() * 4),
+           o_sw = mir.add(pos_dec.size() * sizeof(AttnWork));
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+      return fail(KVOP_ENOMEM, "metadata staging");
+    char* hp = m->stage.p;
+    memcpy(hp + o_pos, pos.data(), pos.size() * 4);
+    if (join) memcpy(hp + o_shift, shift.data(), shift.size() * 4);
+    memcpy(hp + o_work, work.data(), work.size() * sizeof(AttnWork));
+    memcpy(hp + o_suf, suffix.data(), S * 4);
+    if (kind == KVOP_MAP) {
+      memcpy(hp + o_dwork, dwork.data(), dwork.size() * sizeof(AttnWork));
+      memcpy(hp + o_os, own_src.data(), own_src.size() * 4);
+      memcpy(hp + o_od, own_dst.data(), own_dst.size() * 4);
+      memcpy(hp + o_pdec, pos_dec.data(), pos_dec.size() * 4);
+      std::vector<int32_t> ddst(B), dsrc(B);
+      for (int b = 0; b < B; b++) { ddst[b] = b * rows_per_item + S; dsrc[b] = b; }
+      memcpy(hp + o_ddst, ddst.data(), B * 4);
+      memcpy(hp + o_dsrc, dsrc.data(), B * 4);
+    }
+    char* md = (char*)m->meta.p;
+    HIPTRY(hipMemcpyAsync(md, hp, o_ntok, hipMemcpyHostToDevice, st));
+    HIPTRY(hipEventRecord(m->stage.ev, st));
+    m->stage.pending = true;
+
+    // workspace: activations (+ per-layer own rows for maps)
+    size_t act = act_bytes(m, rows, join);
+    size_t own_bytes = kind == KVOP_MAP ? (size_t)c.n_layers * B * rows_per_item * 2 * Hkv * D * e : 0;
+    if (m->ws.reserve(act + align_up(own_bytes, kAlign), st) != hipSuccess)
+      return fail(KVOP_ENOMEM, "activation workspace");
+    LayerBufs bufs = carve(m, (char*)m->ws.p, rows, join);
+    char* ownbuf = (char*)m->ws.p + act;
+    const int64_t own_ld = 2LL * Hkv * D;
+
+    HIPTRY(embed_suffix(m->dt, m->embed, (const int32_t*)(md + o_suf), S, (int)rows, d, c.vocab, bufs.x, st));
+    LayerPlan lp{};
+    lp.rows = (int)rows;
+    lp.pos = (const int32_t*)(md + o_pos);
+    lp.alt_shift = join ? (const int32_t*)(md + o_shift) : nullptr;
+    lp.attn.work = (const AttnWork*)(md + o_work);
+    lp.attn.n_work = (int)work.size();
+    lp.attn.idx = idx;
+    lp.attn.Pmax = Pmax_s;
+    lp.own_from_qkv = true;
+    for (int l = 0; l < c.n_layers; l++) {
+      const bool last = l + 1 == c.n_layers;
+      if (last) {  // only the last suffix row of every item feeds the head
+        lp.n_sel = B;
+        lp.sel_stride = S;
+        lp.sel_off = S - 1;
+      } else {
+        lp.n_sel = (int)rows;
+        lp.sel_stride = 1;
+        lp.sel_off = 0;
+      }
+      kvop_status s = run_layer(m, l, bufs, lp, p->base, p->kvdt, nullptr, 0, st);
+      if (s != KVOP_OK) return s;
+      if (kind == KVOP_MAP) {
+        HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_os),
+                            (const int32_t*)(md + o_od), (int)rows, ownbuf + (size_t)l * B * rows_per_item * own_ld * e,
+                            own_ld, st));
+      }
+    }
+    const float* xlast = bufs.x + (int64_t)(S - 1) * d;
+    if (kind != KVOP_MAP) {
+      HIPTRY(head_filter(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->yes_id, op->no_id,
+                         op->theta_pos, op->theta_neg, logits + (int64_t)w0 * 2, decision ? decision + w0 : nullptr,
+                         st));
+      continue;
+    }
+    // ---- map: step 1 from the suffix's last row, then n_gen - 1 decode steps
+    const int ln = op->label_n;
+    int32_t* ntok = (int32_t*)(md + o_ntok);
+    float* lg = logits + (int64_t)w0 * n_gen * ln;
+    int32_t* tk = tokens_out + (int64_t)w0 * n_gen;
+    HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, lg,
+                    (int64_t)n_gen * ln, tk, n_gen, ntok, st));
+    for (int t = 1; t < n_gen; t++) {
+      // positions of the fed token: L + S + t - 1; it is own row S + t - 1 of its item
+      std::vector<int32_t> pdec(B), ddst(B);
+      for (int b = 0; b < B; b++) {
+        pdec[b] = pos_dec[b] + t - 1;
+        ddst[b] = b * rows_per_item + S + t - 1;
+      }
+      std::vector<AttnWork> dw = dwork;
+      for (int b = 0; b < B; b++) {
+        dw[b].q_pos0 = pdec[b];
+        dw[b].n_own = S + t;
+      }
+      if (m->stage.reserve(mir.size) != hipSuccess) return fail(KVOP_EDEVICE, "metadata staging");
+      memcpy(m->stage.p + o_sp, pdec.data(), B * 4);
+      memcpy(m->stage.p + o_sd, ddst.data(), B * 4);
+      memcpy(m->stage.p + o_sw, dw.data(), dw.size() * sizeof(AttnWork));
+      HIPTRY(hipMemcpyAsync(md + o_sp, m->stage.p + o_sp, mir.size - o_sp, hipMemcpyHostToDevice, st));
+      HIPTRY(hipEventRecord(m->stage.ev, st));
+      m->stage.pending = true;
+      HIPTRY(embed_rows(m->dt, m->embed, ntok, B, d, c.vocab, bufs.x, st));
+      LayerPlan dp{};
+      dp.rows = B;
+      dp.pos = (const int32_t*)(md + o_sp);
+      dp.alt_shift = nullptr;
+      dp.attn.work = (const AttnWork*)(md + o_sw);
+      dp.attn.n_work = B;
+      dp.attn.idx = idx;
+      dp.attn.Pmax = 1;
+      dp.own_from_qkv = false;
+      dp.own_stride = own_ld;
+      dp.own_kcol = 0;
+      dp.own_vcol = Hkv * D;
+      dp.n_sel = B;
+      dp.sel_stride = 1;
+      dp.sel_off = 0;
+      for (int l = 0; l < c.n_layers; l++) {
+        char* own_l = ownbuf + (size_t)l * B * rows_per_item * own_ld * e;
+        dp.own = own_l;
+        // the new token's k, v must be in the own rows before the attention reads them:
+        // run the projection + rotation, append, then attention and the tail
+        const kvop_model::Layer& W = m->layers[l];
+        HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, W.attn_norm, B, d, c.rms_eps, bufs.h, d, st));
+        {
+          GemmShape s{B, qc, d, d, d, qc};
+          HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, s), bufs.h, W.wqkv, bufs.qkv, s, st));
+        }
+        HIPTRY(rope_qk(m->dt, bufs.qkv, qc, B, H, Hkv, D, dp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
+        HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_dsrc),
+                            (const int32_t*)(md + o_sd), B, own_l, own_ld, st));
+        AttnArgs a = dp.attn;
+        a.q = bufs.qkv;
+        a.q_alt = nullptr;
+        a.q_stride = qc;
+        a.own = own_l;
+        a.own_stride = own_ld;
+        a.own_kcol = 0;
+        a.own_vcol = Hkv * D;
+        a.out = bufs.attn;
+        a.out_stride = H * D;
+        a.layer = l;
+        a.n_layers = c.n_layers;
+        a.Hkv = Hkv;
+        a.G = G;
+        a.pool = p->base;
+        a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
+        HIPTRY(attention(m->dt, p->kvdt, D, a, st));
+        {
+          GemmShape s{B, d, H * D, H * D, H * D, d};
+          HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, s), bufs.attn, W.wo, bufs.x, s, st));
+        }
+        HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, W.ffn_norm, B, d, c.rms_eps, bufs.h, d, st));
+        {
+          GemmShape s{B, 2 * F, d, d, d, F};
+          HIPTRY(gemm(m->dt, m->dt, EPI_SWIGLU, gemm_pick_tile(m->dt, EPI_SWIGLU, s), bufs.h, W.wgu, bufs.act, s, st));
+        }
+        {
+          GemmShape s{B, d, F, F, F, d};
+          HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, s), bufs.act, W.wdown, bufs.x, s, st));
+        }
+      }
+      HIPTRY(head_map(m->dt, bufs.x, d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, lg + (int64_t)t * ln,
+                      (int64_t)n_gen * ln, tk + t, n_gen, ntok, st));
+    }
+  }
+  return KVOP_OK;
+}
+
+// ------------------------------------------------------------------ diagnostics / tuning
+int32_t kvop_gemm_num_tiles(int32_t dtype) { return gemm_num_tiles(dtype == KVOP_F32 ? DT_F32 : DT_BF16); }
+
+const char* kvop_gemm_tile_name(int32_t dtype, int32_t tile) {
+  int dt = dtype == KVOP_F32 ? DT_F32 : DT_BF16;
+  if (tile < 0 || tile >= gemm_num_tiles(dt)) return "";
+  return gemm_tile_name(dt, tile);
+}
+
+kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epi, int32_t tile, const void* A, const void* B,
+                            void* Cm, int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb, int64_t ldc,
+                            void* stream) {
+  if (dtype != KVOP_F32 && dtype != KVOP_BF16) return fail(KVOP_EINVAL, "bad dtype");
+  if (epi < 0 || epi > 2 || !A || !B || !Cm || M < 0 || N < 0 || K < 1) return fail(KVOP_EINVAL, "bad arguments");
+  int dt = dtype == KVOP_F32 ? DT_F32 : DT_BF16;
+  int odt = out_dtype == KVOP_F32 ? DT_F32 : DT_BF16;
+  if (dt == DT_F32 && odt != DT_F32) return fail(KVOP_EINVAL, "f32 operands produce f32 results");
+  GemmShape s{M, N, K, lda, ldb, ldc};
+  if (!gemm_tile_ok(dt, tile, s, epi)) return fail(KVOP_EINVAL, "tile cannot run this shape");
+  HIPTRY(gemm(dt, odt, epi, tile, A, B, Cm, s, (hipStream_t)stream));
+  return KVOP_OK;
+}
+
+kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epi, int32_t N, int32_t K, int32_t M, int32_t tile) {
+  int dt = dtype == KVOP_F32 ? DT_F32 : DT_BF16;
+  if (tile < 0 || tile >= gemm_num_tiles(dt) || M < 1) return fail(KVOP_EINVAL, "bad tile");
+  int mb = 0;
+  while ((1 << (mb + 1)) <= M && mb < 30) mb++;
+  gemm_set_tuned(dt, epi, N, K, mb, tile);
+  return KVOP_OK;
+}
+
+kvop_status kvop_debug_read_cache(kvop_pool* p, kvop_handle h, int32_t layer, int32_t kv_head, int32_t kv,
+                                  float* out, void* stream) {
+  if (!p || !out) return fail(KVOP_EINVAL, "null argument");
+  const DocSlot* d = lookup(p, h);
+  if (!d) return fail(KVOP_EBADHANDLE, "handle is not live in this pool");
+  const kvop_model_cfg& c = p->m->cfg;
+  if (layer < 0 || layer >= c.n_layers || kv_head < 0 || kv_head >= c.n_kv_heads || (kv != 0 && kv != 1))
+    return fail(KVOP_EINVAL, "bad layer/head/kv");
+  HIPTRY(read_cache(p->kvdt, p->base + d->off, d->L, c.head_dim, layer, c.n_layers, c.n_kv_heads, kv_head, kv, out,
+                    (hipStream_t)stream));
+  return KVOP_OK;
+}
+
+}  // extern "C"

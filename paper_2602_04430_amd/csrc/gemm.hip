@@ -1,0 +1,275 @@
+// Dense projections of the decoder on MFMA: C = A B^T, both operands K-contiguous.
+//
+// Work split: one workgroup of 4 wavefronts per BM x BN output tile; each wavefront owns
+// a WM x WN sub-tile built from 16x16 MFMA blocks.  K advances in BK slabs staged in LDS
+// (two buffers): the next slab is fetched from global memory into registers while the
+// current one feeds the MFMAs, then written to the other buffer, one barrier per slab.
+// FP32 uses v_mfma_f32_16x16x4f32 (four MFMAs per 16-byte LDS read); BF16 uses the
+// gfx950 v_mfma_f32_16x16x32_bf16.  Accumulation is FP32 in every case.
+// Epilogues: plain store (f32/bf16), FP32 residual add, SwiGLU over interleaved
+// gate/up column blocks.  The workgroup -> tile order is XCD-aware and grouped (see the
+// kernel body) so that concurrently resident workgroups of one XCD share A and B tiles.
+#include <algorithm>
+#include <map>
+#include <tuple>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace kvop {
+
+template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
+                                                      void* __restrict__ Cv, int M, int N, int K, int64_t lda,
+                                                      int64_t ldb, int64_t ldc, int tiles_m) {
+  constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+  constexpr int LDK = BK + VEC;             // padded LDS row (elements)
+  constexpr int CPR = BK / VEC;             // chunks per tile row
+  constexpr int ACH = BM * CPR / 256;
+  constexpr int BCH = BN * CPR / 256;
+  constexpr int MI = WM / 16, NI = WN / 16;
+  constexpr int WN_CNT = BN / WN;
+  constexpr int KSUB = 4 * VEC;             // K consumed per MFMA step group
+  static_assert((BM / WM) * (BN / WN) == 4, "4 wavefronts");
+  static_assert(ACH * 256 == BM * CPR && BCH * 256 == BN * CPR, "tile/thread mismatch");
+  static_assert(EPI != EPI_SWIGLU || (NI % 2 == 0), "swiglu needs gate/up block pairs");
+
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  constexpr int STAGE = (BM + BN) * LDK;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN_CNT, wn = wave % WN_CNT;
+  // Tile order.  The dispatcher hands workgroup b to XCD b % 8; remap so that every XCD
+  // owns one contiguous range of logical tiles, then walk that range in groups of GM
+  // M-tiles x all N-tiles (M fastest inside a group) so that the A and B tiles of
+  // concurrently resident workgroups are shared in that XCD's L2.
+  const int nblk = gridDim.x, bid = blockIdx.x;
+  const int xcd = bid & 7, loc = bid >> 3, q = nblk >> 3, rem = nblk & 7;
+  const int lt = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + loc;
+  const int tiles_n = nblk / tiles_m;
+  constexpr int GM = 8;
+  const int per_group = GM * tiles_n;
+  const int first_m = (lt / per_group) * GM;
+  const int gsz = min(tiles_m - first_m, GM);
+  const int tm = first_m + (lt % per_group) % gsz, tn = (lt % per_group) / gsz;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  u32x4 ra[ACH], rb[BCH];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < ACH; i++) {
+      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
+      int gm = m0 + r, gk = k0 + kc;
+      ra[i] = (gm < M && gk < K) ? *reinterpret_cast<const u32x4*>(A + (int64_t)gm * lda + gk) : u32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < BCH; i++) {
+      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
+      int gn = n0 + r, gk = k0 + kc;
+      rb[i] = (gn < N && gk < K) ? *reinterpret_cast<const u32x4*>(B + (int64_t)gn * ldb + gk) : u32x4{0, 0, 0, 0};
+    }
+  };
+  auto sstore = [&](int buf) {
+    T* As = smem + buf * STAGE;
+    T* Bs = As + BM * LDK;
+#pragma unroll
+    for (int i = 0; i < ACH; i++) {
+      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
+      *reinterpret_cast<u32x4*>(As + r * LDK + kc) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BCH; i++) {
+      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
+      *reinterpret_cast<u32x4*>(Bs + r * LDK + kc) = rb[i];
+    }
+  };
+
+  f32x4 acc[MI][NI];
+#pragma unroll
+  for (int i = 0; i < MI; i++)
+#pragma unroll
+    for (int j = 0; j < NI; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int nk = (K + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  int buf = 0;
+  const int lrow = lane & 15, lk = (lane >> 4) * VEC;
+  for (int kt = 0; kt < nk; kt++) {
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+    const T* As = smem + buf * STAGE + (wm * WM) * LDK;
+    const T* Bs = smem + buf * STAGE + BM * LDK + (wn * WN) * LDK;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += KSUB) {
+      u32x4 af[MI], bfr[NI];
+#pragma unroll
+      for (int i = 0; i < MI; i++) af[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + ks + lk);
+#pragma unroll
+      for (int j = 0; j < NI; j++) bfr[j] = *reinterpret_cast<const u32x4*>(Bs + (j * 16 + lrow) * LDK + ks + lk);
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+#pragma unroll
+          for (int i = 0; i < MI; i++)
+#pragma unroll
+            for (int j = 0; j < NI; j++)
+              acc[i][j] = mfma_f32(__builtin_bit_cast(float, af[i][t]), __builtin_bit_cast(float, bfr[j][t]),
+                                   acc[i][j]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < MI; i++)
+#pragma unroll
+          for (int j = 0; j < NI; j++)
+            acc[i][j] = mfma_bf16(__builtin_bit_cast(u16x8, af[i]), __builtin_bit_cast(u16x8, bfr[j]), acc[i][j]);
+      }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // epilogue: lane holds C[row0 + 4*(lane/16) + r][col0 + lane%16]
+  const int rbase = m0 + wm * WM + (lane >> 4) * 4;
+  const int cbase = n0 + wn * WN + (lane & 15);
+  if constexpr (EPI == EPI_SWIGLU) {
+    TO* C = reinterpret_cast<TO*>(Cv);
+    // column block (n0 + wn*WN)/16 + j: even = gate, odd = up of the same 16 features
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+      for (int j = 0; j < NI; j += 2) {
+        int f = ((n0 + wn * WN) / 32 + j / 2) * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          int row = rbase + i * 16 + r;
+          if (row < M && 2 * f < N) {
+            float gte = acc[i][j][r], up = acc[i][j + 1][r];
+            C[(int64_t)row * ldc + f] = from_f32<TO>(silu(gte) * up);
+          }
+        }
+      }
+  } else {
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+      for (int j = 0; j < NI; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          int row = rbase + i * 16 + r, col = cbase + j * 16;
+          if (row < M && col < N) {
+            if constexpr (EPI == EPI_ADD) {
+              float* C = reinterpret_cast<float*>(Cv);
+              C[(int64_t)row * ldc + col] += acc[i][j][r];
+            } else {
+              TO* C = reinterpret_cast<TO*>(Cv);
+              C[(int64_t)row * ldc + col] = from_f32<TO>(acc[i][j][r]);
+            }
+          }
+        }
+  }
+}
+
+// ------------------------------------------------------------------ tile table
+struct TileCfg {
+  int BM, BN, BK, WM, WN;
+  const char* name;
+};
+static const TileCfg kF32Tiles[] = {
+    {128, 128, 32, 64, 64, "f32_128x128x32_w64x64"},
+    {64, 128, 32, 32, 64, "f32_64x128x32_w32x64"},
+    {128, 64, 32, 64, 32, "f32_128x64x32_w64x32"},
+};
+static const TileCfg kBf16Tiles[] = {
+    {128, 128, 64, 64, 64, "bf16_128x128x64_w64x64"},
+    {256, 128, 64, 128, 64, "bf16_256x128x64_w128x64"},
+    {128, 256, 64, 64, 128, "bf16_128x256x64_w64x128"},
+    {64, 128, 64, 32, 64, "bf16_64x128x64_w32x64"},
+};
+
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 3 : 4; }
+const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
+
+static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
+
+bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
+  if (t < 0 || t >= gemm_num_tiles(dt)) return false;
+  const TileCfg& c = tile_cfg(dt, t);
+  int vec = dt == DT_F32 ? 4 : 8;
+  if (s.K % vec || s.lda % vec || s.ldb % vec) return false;
+  if (epi == EPI_SWIGLU && (s.N % 32 || (c.WN % 32))) return false;
+  return true;
+}
+
+template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN>
+static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
+  int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
+  size_t lds = 2 * (size_t)(BM + BN) * (BK + 16 / sizeof(T)) * sizeof(T);
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(256), lds, st, (const T*)A, (const T*)B, C, s.M, s.N, s.K,
+                     s.lda, s.ldb, s.ldc, tiles_m);
+  return hipGetLastError();
+}
+
+template <typename T, typename TO, int EPI>
+static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    switch (tile) {
+      case 0: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64>(A, B, C, s, st);
+      case 1: return launch_t<T, TO, EPI, 64, 128, 32, 32, 64>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 128, 64, 32, 64, 32>(A, B, C, s, st);
+    }
+  } else {
+    switch (tile) {
+      case 0: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64>(A, B, C, s, st);
+      case 1: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64>(A, B, C, s, st);
+      case 2: return launch_t<T, TO, EPI, 128, 256, 64, 64, 128>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64>(A, B, C, s, st);
+    }
+  }
+}
+
+hipError_t gemm(int dt, int out_dt, int epi, int tile, const void* A, const void* B, void* C, const GemmShape& s,
+                hipStream_t st) {
+  if (s.M <= 0 || s.N <= 0) return hipSuccess;
+  if (!gemm_tile_ok(dt, tile, s, epi)) return hipErrorInvalidValue;
+  if (dt == DT_F32) {
+    if (epi == EPI_ADD) return launch_cfg<float, float, EPI_ADD>(tile, A, B, C, s, st);
+    if (epi == EPI_SWIGLU) return launch_cfg<float, float, EPI_SWIGLU>(tile, A, B, C, s, st);
+    return launch_cfg<float, float, EPI_STORE>(tile, A, B, C, s, st);
+  }
+  if (epi == EPI_ADD) return launch_cfg<bf16_t, float, EPI_ADD>(tile, A, B, C, s, st);
+  if (epi == EPI_SWIGLU) return launch_cfg<bf16_t, bf16_t, EPI_SWIGLU>(tile, A, B, C, s, st);
+  if (out_dt == DT_F32) return launch_cfg<bf16_t, float, EPI_STORE>(tile, A, B, C, s, st);
+  return launch_cfg<bf16_t, bf16_t, EPI_STORE>(tile, A, B, C, s, st);
+}
+
+// ------------------------------------------------------------------ tile choice
+// Tuned winners keyed by (dtype, epilogue, N, K, M bucket); filled by the autotuner.
+static std::map<std::tuple<int, int, int, int, int>, int>& tuned() {
+  static std::map<std::tuple<int, int, int, int, int>, int> t;
+  return t;
+}
+static int mbucket(int M) {
+  int b = 0;
+  while ((1 << (b + 1)) <= M && b < 30) b++;
+  return b;
+}
+void gemm_set_tuned(int dt, int epi, int N, int K, int mb, int tile) { tuned()[{dt, epi, N, K, mb}] = tile; }
+
+int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
+  auto it = tuned().find({dt, epi, s.N, s.K, mbucket(s.M)});
+  if (it != tuned().end() && gemm_tile_ok(dt, it->second, s, epi)) return it->second;
+  if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
+  if (s.M <= 128) return 3;
+  return 0;
+}
+
+}  // namespace kvop

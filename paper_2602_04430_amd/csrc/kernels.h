@@ -1,0 +1,124 @@
+// Launchers of the gfx950 kernels (host side).  Each returns hipSuccess or the first
+// HIP error of its launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kvop {
+
+enum Dt { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
+enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_SWIGLU = 2 };
+
+// ---------------------------------------------------------------- GEMM (C = A B^T)
+// A [M, K] (lda), B [N, K] (ldb), both in `dt` (f32 or bf16); FP32 accumulation.
+//   EPI_STORE : C[M, N] (ldc) in `out_dt`
+//   EPI_ADD   : C (FP32) += A B^T           (residual add)
+//   EPI_SWIGLU: B rows interleaved in blocks of 16 (16 gate rows, then the 16 matching
+//               up rows); C[M, N/2] (ldc) in `out_dt` = silu(gate) * up
+struct GemmShape {
+  int M, N, K;
+  int64_t lda, ldb, ldc;
+};
+// Tile configurations (autotuner candidates); see gemm.hip.
+int gemm_num_tiles(int dt);
+const char* gemm_tile_name(int dt, int tile);
+bool gemm_tile_ok(int dt, int tile, const GemmShape& s, int epi);
+hipError_t gemm(int dt, int out_dt, int epi, int tile, const void* A, const void* B, void* C, const GemmShape& s,
+                hipStream_t st);
+// default tile for a shape (from the tuned table when present)
+int gemm_pick_tile(int dt, int epi, const GemmShape& s);
+void gemm_set_tuned(int dt, int epi, int N, int K, int mbucket, int tile);
+
+// ---------------------------------------------------------------- attention
+// One work item = one (query block, key sources) unit; executed for every kv head.
+struct AttnWork {
+  int64_t off_a;      // byte offset of document A's cache region in the pool (-1: none)
+  int64_t off_b;      // byte offset of document B's region (join), -1 if none
+  int64_t idx_a;      // offset of A's retained list in the index array, -1 = rows 0..n_a-1
+  int64_t idx_b;      // offset of B's retained list, -1 = rows 0..n_b-1
+  int32_t L_a, L_b;   // document lengths (region layout; B's key positions are L_a + p)
+  int32_t n_a, n_b;   // keys taken from A and B
+  int32_t q_row0;     // activation row of query position 0 of this item
+  int32_t q_pos0;     // absolute position of query position 0
+  int32_t n_q;        // query positions in this item (<= Pmax)
+  int32_t own_row0;   // first own row (suffix/generated keys) in the own-row buffer
+  int32_t n_own;      // own keys; own key j sits at position own_pos0 + j
+  int32_t own_pos0;
+};
+
+struct AttnArgs {
+  const AttnWork* work;
+  int n_work;
+  const uint8_t* pool;
+  const int32_t* idx;
+  const void* q;       // queries [rows][q_stride], head hq at column hq*D (rotated)
+  const void* q_alt;   // join: queries rotated at (position - L_a), same layout; may be null
+  int64_t q_stride;
+  const void* own;     // own keys/values [rows][own_stride]; k of kv head h at own_kcol + h*D
+  int64_t own_stride;
+  int own_kcol, own_vcol;
+  void* out;           // [rows][out_stride], head hq at column hq*D
+  int64_t out_stride;
+  int layer, n_layers, Hkv, G, Pmax;
+  float scale_log2;    // log2(e) / sqrt(D)
+};
+// cdt: compute/query dtype (f32 or bf16); kvdt: cache dtype (f32 with f32; bf16/fp8 with bf16)
+hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- elementwise / small kernels
+// x[row] = embed[tok[row]] (embed in `dt`), FP32 output; ids clamped to [0, V)
+hipError_t embed_rows(int dt, const void* embed, const int32_t* tok, int n_rows, int d, int vocab, float* x,
+                      hipStream_t st);
+// embed rows whose token is suffix[row % S] (op_eval input)
+hipError_t embed_suffix(int dt, const void* embed, const int32_t* suffix, int S, int n_rows, int d, int vocab,
+                        float* x, hipStream_t st);
+// y[row] = rmsnorm(x[row]) * g, x FP32 with row stride ldx, y in `dt` with stride ldy
+hipError_t rmsnorm_rows(int dt, const float* x, int64_t ldx, const float* g, int n_rows, int d, float eps, void* y,
+                        int64_t ldy, hipStream_t st);
+// rotary embedding in place on q heads and k heads of a qkv buffer (dt), row positions
+// pos[row]; when q_alt != null also writes q rotated at pos[row] - alt_shift[row] into q_alt
+hipError_t rope_qk(int dt, void* qkv, int64_t ld, int n_rows, int H, int Hkv, int D, const int32_t* pos,
+                   const float* cos_tab, const float* sin_tab, void* q_alt, const int32_t* alt_shift,
+                   hipStream_t st);
+// kv_build: rotate q (in place) and k of document rows and write k, v into the cache
+struct KvBlock {      // 16 consecutive rows of one document
+  int64_t off;        // document region byte offset
+  int32_t L;          // document length
+  int32_t p0;         // first position of the block
+  int32_t row0;       // activation row of position p0
+  int32_t pad;
+};
+hipError_t rope_write_kv(int dt, int kvdt, void* qkv, int64_t ld, const KvBlock* blocks, int n_blocks, int H,
+                         int Hkv, int D, int layer, int n_layers, const float* cos_tab, const float* sin_tab,
+                         uint8_t* pool, hipStream_t st);
+// map decode bookkeeping: copy k, v of rows into a per-layer own-row buffer
+hipError_t copy_kv_rows(int dt, const void* qkv, int64_t ld, int kcol, int n_cols, const int32_t* src_rows,
+                        const int32_t* dst_rows, int n, void* dst, int64_t ldd, hipStream_t st);
+// pooled[doc] = mean over the document's rows of rmsnorm(x)*g (FP32); row_off[n_docs+1]
+// are row offsets into x; inv_scratch holds n_rows floats
+hipError_t pooled_mean(const float* x, int d, const int64_t* row_off, int n_docs, int n_rows, const float* g,
+                       float eps, float* inv_scratch, float* pooled, hipStream_t st);
+// filter/join head: y = rmsnorm(x[row_of_item]) * g; logits (yes, no); log-odds decision
+hipError_t head_filter(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
+                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, float* logits,
+                       int8_t* decision, hipStream_t st);
+// map head: logits over [lo, lo+n) and argmax (lowest id on ties)
+hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
+                    const void* head, int lo, int n, float* logits, int64_t ld_logits, int32_t* tok_out,
+                    int64_t ld_tok, int32_t* next_tok, hipStream_t st);
+// index-list validation: counts lists that are unsorted or out of range into *bad
+struct ListCheck {
+  int64_t off;
+  int32_t n, L;
+};
+hipError_t validate_lists(const int32_t* idx, const ListCheck* lists, int n_lists, int* bad, hipStream_t st);
+// weight conversion: dst (dt) = src (f32); for interleave16 != 0 the rows of two [F, d]
+// matrices (src, src2) are interleaved in blocks of 16
+hipError_t convert_weights(int dt, const float* src, const float* src2, int64_t rows, int64_t cols, void* dst,
+                           int interleave16, hipStream_t st);
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+// decode L rows of one cached (layer, head, K or V) block to FP32
+hipError_t read_cache(int kvdt, const uint8_t* region, int L, int D, int layer, int n_layers, int Hkv, int h, int kv,
+                      float* out, hipStream_t st);
+
+}  // namespace kvop

@@ -1,0 +1,200 @@
+"""Thin Python binding of the kvop C ABI (argument marshalling only).
+
+Every function keeps the C name and forwards to libkvop.so; device buffers are passed as
+torch tensors (their data pointers), host arrays as numpy arrays, and the stream is the
+current torch stream unless given.  Every computation happens in the HIP library: if it
+is not built, importing a function raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkvop.so")
+
+KVOP_OK, KVOP_EINVAL, KVOP_ENOMEM, KVOP_EBADHANDLE, KVOP_EDEVICE = range(5)
+KVOP_F32, KVOP_BF16 = 0, 1
+KVOP_KV_F32, KVOP_KV_BF16, KVOP_KV_FP8 = 0, 1, 2
+KVOP_FILTER, KVOP_MAP, KVOP_JOIN = 0, 1, 2
+KVOP_FLAG_ANY_COUNT = 1
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBADHANDLE", 4: "EDEVICE"}
+
+
+class KvopError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class kvop_model_cfg(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("d_model", C.c_int32), ("n_heads", C.c_int32),
+                ("n_kv_heads", C.c_int32), ("head_dim", C.c_int32), ("d_ffn", C.c_int32),
+                ("vocab", C.c_int32), ("rms_eps", C.c_float), ("rope_theta", C.c_float)]
+
+
+class kvop_op(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("suffix_host", C.POINTER(C.c_int32)), ("suffix_len", C.c_int32),
+                ("yes_id", C.c_int32), ("no_id", C.c_int32), ("theta_pos", C.c_float),
+                ("theta_neg", C.c_float), ("label_lo", C.c_int32), ("label_n", C.c_int32),
+                ("n_gen", C.c_int32), ("flags", C.c_uint32)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "kvop_last_error": (C.c_char_p, []),
+    "kvop_weights_numel": (C.c_int64, [C.POINTER(kvop_model_cfg)]),
+    "kvop_model_create": (C.c_int, [C.POINTER(kvop_model_cfg), _P, C.c_int64, C.c_int, _P, C.POINTER(_P)]),
+    "kvop_model_destroy": (C.c_int, [_P]),
+    "kvop_pool_create": (C.c_int, [_P, C.c_int, C.c_uint64, C.POINTER(_P)]),
+    "kvop_pool_destroy": (C.c_int, [_P]),
+    "kvop_doc_bytes": (C.c_uint64, [_P, C.c_int64]),
+    "kvop_pool_stats": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]),
+    "kvop_kv_build": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P]),
+    "kvop_kv_release": (C.c_int, [_P, _P, C.c_int32]),
+    "kvop_op_eval": (C.c_int, [_P, C.POINTER(kvop_op), C.c_float, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
+    "kvop_gemm_num_tiles": (C.c_int32, [C.c_int32]),
+    "kvop_gemm_tile_name": (C.c_char_p, [C.c_int32, C.c_int32]),
+    "kvop_debug_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P]),
+    "kvop_gemm_set_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "kvop_debug_read_cache": (C.c_int, [_P, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+}
+_lib_handle = None
+
+
+def lib():
+    """Load libkvop.so (built in-tree by build_lib); raise if it is missing."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2602_04430_amd.build_lib`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+        _lib_handle = h
+    return _lib_handle
+
+
+def _check(status: int):
+    if status != KVOP_OK:
+        raise KvopError(status, lib().kvop_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else int(t.data_ptr()))
+
+
+def _host(a, dtype):
+    arr = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+    return arr, arr.ctypes.data_as(C.c_void_p)
+
+
+def make_cfg(shape) -> kvop_model_cfg:
+    return kvop_model_cfg(shape.n_layers, shape.d_model, shape.n_heads, shape.n_kv_heads, shape.head_dim,
+                          shape.d_ffn, shape.vocab, shape.rms_eps, shape.rope_theta)
+
+
+def kvop_weights_numel(cfg: kvop_model_cfg) -> int:
+    return int(lib().kvop_weights_numel(C.byref(cfg)))
+
+
+def kvop_model_create(cfg: kvop_model_cfg, weights_dev, compute: int, stream=None) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib().kvop_model_create(C.byref(cfg), _dptr(weights_dev), int(weights_dev.numel()), compute,
+                                   _stream(stream), C.byref(out)))
+    return out
+
+
+def kvop_model_destroy(model) -> None:
+    _check(lib().kvop_model_destroy(model))
+
+
+def kvop_pool_create(model, kv_dtype: int, nbytes: int) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib().kvop_pool_create(model, kv_dtype, int(nbytes), C.byref(out)))
+    return out
+
+
+def kvop_pool_destroy(pool) -> None:
+    _check(lib().kvop_pool_destroy(pool))
+
+
+def kvop_doc_bytes(pool, L: int) -> int:
+    return int(lib().kvop_doc_bytes(pool, int(L)))
+
+
+def kvop_pool_stats(pool):
+    u, c, n = C.c_uint64(), C.c_uint64(), C.c_int32()
+    _check(lib().kvop_pool_stats(pool, C.byref(u), C.byref(c), C.byref(n)))
+    return int(u.value), int(c.value), int(n.value)
+
+
+def kvop_kv_build(pool, tokens_dev, offsets: Sequence[int], pooled_dev=None, stream=None) -> np.ndarray:
+    """Returns the uint64 handles of the built documents."""
+    offs, po = _host(offsets, np.int64)
+    n = len(offs) - 1
+    handles = np.zeros(max(n, 0), np.uint64)
+    _check(lib().kvop_kv_build(pool, _dptr(tokens_dev), po, n, _stream(stream),
+                               handles.ctypes.data_as(C.c_void_p), _dptr(pooled_dev)))
+    return handles
+
+
+def kvop_kv_release(pool, handles) -> None:
+    h, hp = _host(handles, np.uint64)
+    _check(lib().kvop_kv_release(pool, hp, len(h)))
+
+
+def make_op(kind: int, suffix, yes_id: int = 1, no_id: int = 0, theta_pos: float = 0.0, theta_neg: float = 0.0,
+            label_lo: int = 0, label_n: int = 0, n_gen: int = 1, flags: int = 0):
+    suf = np.ascontiguousarray(np.asarray(suffix, np.int32))
+    op = kvop_op(kind, suf.ctypes.data_as(C.POINTER(C.c_int32)), len(suf), yes_id, no_id, theta_pos, theta_neg,
+                 label_lo, label_n, n_gen, flags)
+    op._keep = suf  # keep the suffix alive with the descriptor
+    return op
+
+
+def kvop_op_eval(pool, op: kvop_op, r: float, idx_dev, idx_offsets: Sequence[int], handles, logits_dev,
+                 decision_dev=None, tokens_dev=None, stream=None) -> None:
+    offs, po = _host(idx_offsets, np.int64)
+    h, hp = _host(handles, np.uint64)
+    n_items = len(h) // (2 if op.kind == KVOP_JOIN else 1)
+    _check(lib().kvop_op_eval(pool, C.byref(op), float(r), _dptr(idx_dev), po, hp, n_items, _stream(stream),
+                              _dptr(logits_dev), _dptr(decision_dev), _dptr(tokens_dev)))
+
+
+def kvop_gemm_num_tiles(dtype: int) -> int:
+    return int(lib().kvop_gemm_num_tiles(dtype))
+
+
+def kvop_gemm_tile_name(dtype: int, tile: int) -> str:
+    return lib().kvop_gemm_tile_name(dtype, tile).decode()
+
+
+def kvop_debug_gemm(dtype: int, out_dtype: int, epilogue: int, tile: int, A, B, Cm, M: int, N: int, K: int,
+                    lda: int, ldb: int, ldc: int, stream=None) -> None:
+    _check(lib().kvop_debug_gemm(dtype, out_dtype, epilogue, tile, _dptr(A), _dptr(B), _dptr(Cm), M, N, K, lda, ldb,
+                                 ldc, _stream(stream)))
+
+
+def kvop_gemm_set_tile(dtype: int, epilogue: int, N: int, K: int, M: int, tile: int) -> None:
+    _check(lib().kvop_gemm_set_tile(dtype, epilogue, N, K, M, tile))
+
+
+def kvop_debug_read_cache(pool, handle, layer: int, kv_head: int, kv: int, out_dev, stream=None) -> None:
+    _check(lib().kvop_debug_read_cache(pool, C.c_uint64(int(handle)), layer, kv_head, kv, _dptr(out_dev),
+                                       _stream(stream)))

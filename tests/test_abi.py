@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every symbol include/kvop.h declares; host-only
+calls (no GPU needed) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2602_04430_amd import kvop as K
+from paper_2602_04430_amd import synth
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "kvop.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kvop_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "kvop_op_eval" in names and "kvop_kv_build" in names
+    lib = ctypes.CDLL(K.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_function():
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(K, n) and n not in ("kvop_last_error",)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("shape", [synth.TINY, synth.SCALE])
+def test_weights_numel_matches_packing(shape):
+    assert K.kvop_weights_numel(K.make_cfg(shape)) == shape.numel()
+
+
+def test_model_create_rejects_bad_shapes_before_touching_the_device():
+    bad = K.make_cfg(synth.TINY)
+    bad.head_dim = 48
+    out = ctypes.c_void_p()
+    st = K.lib().kvop_model_create(ctypes.byref(bad), ctypes.c_void_p(1), 1, 0, None, ctypes.byref(out))
+    assert st == K.KVOP_EINVAL and b"head_dim" in K.lib().kvop_last_error()
+    bad = K.make_cfg(synth.TINY)
+    bad.n_kv_heads = 3
+    st = K.lib().kvop_model_create(ctypes.byref(bad), ctypes.c_void_p(1), 1, 0, None, ctypes.byref(out))
+    assert st == K.KVOP_EINVAL
+    good = K.make_cfg(synth.TINY)
+    st = K.lib().kvop_model_create(ctypes.byref(good), ctypes.c_void_p(1), 5, 0, None, ctypes.byref(out))
+    assert st == K.KVOP_EINVAL and b"count" in K.lib().kvop_last_error()
+
+
+def test_gemm_tile_table_is_named():
+    for dt in (K.KVOP_F32, K.KVOP_BF16):
+        n = K.kvop_gemm_num_tiles(dt)
+        assert n >= 3
+        names = [K.kvop_gemm_tile_name(dt, t) for t in range(n)]
+        assert len(set(names)) == n and all(names)

@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle (and, for the
+projections, against a float64 product of the same rounded operands)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import model as om
+from paper_2602_04430_amd import kvop as K
+from paper_2602_04430_amd import synth
+from tests.gpu_common import BOUND, E_F32, Engine, decisions_agree_outside_band, say
+
+pytestmark = pytest.mark.gpu
+
+MICRO_GQA = synth.ModelShape(n_layers=2, d_model=256, n_heads=4, n_kv_heads=2, head_dim=64, d_ffn=512, vocab=512)
+
+
+# ----------------------------------------------------------------------------- projections
+
+def _bf16(x):
+    return x.to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_gemm_every_tile_matches_float64(device, dtype, epi):
+    rng = np.random.default_rng(0)
+    dt = K.KVOP_F32 if dtype == "f32" else K.KVOP_BF16
+    for M, N, Kd in [(1, 128, 64), (77, 256, 192), (300, 384, 256), (1000, 128, 512)]:
+        A = torch.from_numpy(rng.standard_normal((M, Kd)).astype(np.float32))
+        B = torch.from_numpy(rng.standard_normal((N, Kd)).astype(np.float32))
+        if dtype == "bf16":
+            A, B = _bf16(A).float(), _bf16(B).float()
+        ref = A.double() @ B.double().T
+        if epi == 2:
+            g = ref.reshape(M, N // 32, 2, 16)
+            ref = (torch.nn.functional.silu(g[:, :, 0]) * g[:, :, 1]).reshape(M, N // 2)
+        C0 = torch.from_numpy(rng.standard_normal(ref.shape).astype(np.float32))
+        if epi == 1:
+            ref = ref + C0.double()
+        for tile in range(K.kvop_gemm_num_tiles(dt)):
+            say("gemm", dtype, epi, M, N, Kd, K.kvop_gemm_tile_name(dt, tile))
+            Ad = (A if dtype == "f32" else _bf16(A)).to(device)
+            Bd = (B if dtype == "f32" else _bf16(B)).to(device)
+            out_f32 = dtype == "f32" or epi == 1
+            Cd = C0.clone().to(device) if out_f32 else _bf16(C0).to(device)
+            ldc = ref.shape[1]
+            K.kvop_debug_gemm(dt, K.KVOP_F32 if out_f32 else K.KVOP_BF16, epi, tile, Ad, Bd, Cd, M, N, Kd, Kd, Kd, ldc)
+            torch.cuda.synchronize()
+            got = Cd.float().cpu().double()
+            scale = max(1.0, float(ref.abs().max()))
+            tol = 2e-5 * np.sqrt(Kd) * scale if out_f32 else 1.6e-2 * scale
+            err = float((got - ref).abs().max())
+            assert err <= tol, (dtype, epi, M, N, Kd, tile, err, tol)
+
+
+# ----------------------------------------------------------------------------- kv_build
+
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
+def test_kv_build_cache_rows_match_oracle(device, compute, kv):
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 3, gain_jitter=0.1)
+    docs = synth.make_docs_uniform(6, 1, 70, shape.vocab, seed=3)
+    eng = Engine(shape, w, compute, kv)
+    say("kv_build", compute, kv, docs.lengths.tolist())
+    handles, pooled = eng.build(docs, pooled=True)
+    m = om.Model(shape, w)
+    tol = {"f32": 2e-5, "bf16": 3e-2, "fp8": 8e-2}[kv]
+    for i in range(len(docs.lengths)):
+        ref = om.kv_build(m, docs.doc(i))
+        L = int(docs.lengths[i])
+        out = torch.empty(L, shape.head_dim, dtype=torch.float32, device=device)
+        for l in range(shape.n_layers):
+            for h in range(shape.n_kv_heads):
+                for kvsel, R in ((0, ref.K), (1, ref.V)):
+                    K.kvop_debug_read_cache(eng.pool, handles[i], l, h, kvsel, out)
+                    torch.cuda.synchronize()
+                    got = out.cpu().numpy().astype(np.float64)
+                    exp = R[l, h]
+                    err = np.max(np.abs(got - exp)) / max(1e-6, np.max(np.abs(exp)))
+                    assert err <= tol, (i, l, h, kvsel, err)
+        perr = np.max(np.abs(pooled[i].cpu().numpy() - ref.pooled)) / np.max(np.abs(ref.pooled))
+        assert perr <= {"f32": 2e-5, "bf16": 3e-2, "fp8": 5e-2}[kv], (i, perr)
+    eng.close()
+
+
+# ----------------------------------------------------------------------------- filter
+
+def _golden_tiny():
+    path = os.path.join(os.path.dirname(__file__), "golden", "tiny_filter_fp64.txt")
+    return np.loadtxt(path, comments="#")
+
+
+def test_tiny_filter_fp32_all_tuples_match_stored_oracle(device):
+    """The small plain-filter workload (64 tuples, r = 1) against the stored FP64 values."""
+    wl = synth.tiny_filter(0)
+    w = synth.make_weights(wl.shape, 0)
+    eng = Engine(wl.shape, w, "f32", "f32")
+    handles = eng.build(wl.docs)
+    idx, offs = synth.full_lists(wl.docs.lengths)
+    say("tiny filter f32")
+    lg, dec = eng.filter(handles, idx, offs, wl.suffix)
+    ref = _golden_tiny()
+    err = np.max(np.abs(lg - ref[:, 1:3]))
+    say("tiny filter f32 max-abs logit error", err)
+    assert err <= E_F32
+    bad, band = decisions_agree_outside_band(ref[:, 3], dec, E_F32)
+    assert bad == 0
+    assert set(np.unique(dec)) <= {0, 1}
+    eng.close()
+
+
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
+@pytest.mark.parametrize("r", [1.0, 0.5, 0.1])
+def test_filter_gqa_retention_matches_oracle(device, compute, kv, r):
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 5, gain_jitter=0.1)
+    docs = synth.make_docs_uniform(20, 1, 150, shape.vocab, seed=5)
+    suffix = synth.suffix_tokens(21, shape.vocab, seed=5)
+    eng = Engine(shape, w, compute, kv)
+    handles = eng.build(docs)
+    idx, offs = synth.retained_lists(docs.lengths, r, seed=5)
+    say("filter", compute, kv, r)
+    lg, dec = eng.filter(handles, idx, offs, suffix, r=r)
+    m = om.Model(shape, w)
+    E = BOUND[(compute, kv)]
+    ref_lo = []
+    for i in range(len(docs.lengths)):
+        c = om.kv_build(m, docs.doc(i))
+        res = om.filter_eval(m, c, idx[offs[i]:offs[i + 1]], suffix, synth.YES_ID, synth.NO_ID)
+        err = np.max(np.abs(lg[i] - res.logits))
+        assert err <= E, (i, err, E)
+        ref_lo.append(res.log_odds)
+    bad, band = decisions_agree_outside_band(ref_lo, dec, E)
+    assert bad == 0
+    eng.close()
+
+
+# ----------------------------------------------------------------------------- error paths
+
+def test_error_paths(device):
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 6)
+    docs = synth.make_docs_uniform(4, 10, 40, shape.vocab, seed=6)
+    suffix = synth.suffix_tokens(5, shape.vocab, seed=6)
+    eng = Engine(shape, w, "f32", "f32", pool_bytes=4 << 20)
+    handles = eng.build(docs)
+    idx, offs = synth.full_lists(docs.lengths)
+
+    def status(fn):
+        try:
+            fn()
+        except K.KvopError as e:
+            return e.status
+        return K.KVOP_OK
+
+    assert status(lambda: eng.filter(handles, idx, offs, suffix, r=0.0)) == K.KVOP_EINVAL
+    assert status(lambda: eng.filter(handles, idx, offs, suffix, r=0.5)) == K.KVOP_EINVAL      # wrong count
+    bad = idx.copy()
+    bad[1], bad[2] = bad[2], bad[1]                                                            # unsorted
+    assert status(lambda: eng.filter(handles, bad, offs, suffix)) == K.KVOP_EINVAL
+    oob = idx.copy()
+    oob[offs[1] - 1] = docs.lengths[0] + 5                                                     # out of range
+    assert status(lambda: eng.filter(handles, oob, offs, suffix, flags=K.KVOP_FLAG_ANY_COUNT)) == K.KVOP_EINVAL
+    # a valid call still works after the rejected ones
+    lg, dec = eng.filter(handles, idx, offs, suffix)
+    assert np.all(np.isfinite(lg))
+    K.kvop_kv_release(eng.pool, handles[:1])
+    assert status(lambda: eng.filter(handles, idx, offs, suffix)) == K.KVOP_EBADHANDLE
+    assert status(lambda: K.kvop_kv_release(eng.pool, handles[:1])) == K.KVOP_EBADHANDLE
+    big = synth.make_docs_uniform(200, 400, 400, shape.vocab, seed=7)                          # too big for 4 MiB
+    u0 = K.kvop_pool_stats(eng.pool)
+    assert status(lambda: eng.build(big)) == K.KVOP_ENOMEM
+    assert K.kvop_pool_stats(eng.pool) == u0                                                   # nothing leaked
+    eng.close()
