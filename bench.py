@@ -1,0 +1,272 @@
+#!/usr/bin/env python3
+"""Throughput of the KV-cached semantic filter on one MI355X.
+
+Workload: the 16-layer d_model-2048 GQA decoder (16 query / 8 kv heads of 128, SwiGLU
+5632, vocab 32000, normal(0, 0.02) weights, seed 0) over 4096 seeded synthetic documents
+with log-normal lengths (median 512, sigma 1, clipped to [64, 4096]) and one 32-token
+instruction suffix.  Caches are built once (kv_build, timed separately), then one step
+is one op_eval of the filter over all 4096 documents at retention r; the retained rows
+are seeded index lists (first four rows always, the rest uniform, sorted).
+
+Paths timed: BF16 weights/activations with a BF16 cache (the headline), the same with an
+FP8-E4M3 cache, and the plain FP32 path (FP32 cache; it exceeds HBM, so it runs in waves
+that each build, evaluate and release part of the documents; only op_eval is timed).
+Inputs are resident in HBM before every timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tuples/sec KV-cached semantic filter, BF16+proxy vs FP32 plain at ≤1% disagreement"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_F32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096, help="documents (the workload has 4096)")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 path")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-cache variant")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="documents the oracle is timed on")
+    ap.add_argument("--json-out", default=None)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the operator path has no multi-GPU mode (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2602_04430_amd import kvop as K
+    from paper_2602_04430_amd import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    shape = synth.SCALE
+    t0 = time.time()
+    wl = synth.scale_filter(0, n=args.n)
+    docs = wl.docs
+    n = len(docs.lengths)
+    log(f"workload: {n} docs, sum L = {int(docs.lengths.sum())}, mean L = {docs.lengths.mean():.1f}")
+    w = synth.make_weights(shape, 0)
+    flat = torch.from_numpy(synth.pack_weights(shape, w)).to(dev)
+    log(f"weights ready ({time.time() - t0:.1f} s)")
+    cfg = K.make_cfg(shape)
+    toks = torch.from_numpy(docs.tokens).to(dev)
+    lists = {}
+    for r in wl.r_grid:
+        idx, offs = synth.retained_lists(docs.lengths, r, seed=0)
+        lists[r] = (torch.from_numpy(idx).to(dev), offs)
+    op = K.make_op(K.KVOP_FILTER, wl.suffix, synth.YES_ID, synth.NO_ID)
+    stream = torch.cuda.current_stream()
+
+    def timed_eval(pool, r, handles, sel=None, steps=1, warmup=0):
+        """op_eval over the documents; returns (ms per step, logits, decisions)."""
+        idx, offs = lists[r]
+        if sel is not None:
+            # restrict to a contiguous range of documents [a, b)
+            a, b = sel
+            idx = idx[int(offs[a]):int(offs[b])]
+            offs = offs[a:b + 1] - offs[a]
+        m = len(handles)
+        lg = torch.empty(m, 2, dtype=torch.float32, device=dev)
+        dec = torch.empty(m, dtype=torch.int8, device=dev)
+        for _ in range(warmup):
+            K.kvop_op_eval(pool, op, r, idx, offs, handles, lg, dec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            K.kvop_op_eval(pool, op, r, idx, offs, handles, lg, dec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, lg.cpu().numpy().astype(np.float64), dec.cpu().numpy()
+
+    def build(pool, a, b, pooled=None):
+        offs = docs.offsets[a:b + 1] - docs.offsets[a]
+        sub = toks[int(docs.offsets[a]):int(docs.offsets[b])]
+        torch.cuda.synchronize()
+        tb = time.time()
+        h = K.kvop_kv_build(pool, sub, offs, pooled)
+        torch.cuda.synchronize()
+        return h, time.time() - tb
+
+    result = {}
+    # ------------------------------------------------------------------ BF16 path
+    mb = K.kvop_model_create(cfg, flat, K.KVOP_BF16)
+    probe = K.kvop_pool_create(mb, K.KVOP_KV_BF16, 1 << 20)
+    need = sum(K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths)
+    K.kvop_pool_destroy(probe)
+    free = torch.cuda.mem_get_info()[0]
+    log(f"BF16 cache needs {need / 2**30:.1f} GiB, free {free / 2**30:.1f} GiB")
+    pool = K.kvop_pool_create(mb, K.KVOP_KV_BF16, need + (64 << 20))
+    pooled = torch.empty(n, shape.d_model, dtype=torch.float32, device=dev)
+    hb, t_build = build(pool, 0, n, pooled)
+    tokens_total = int(docs.lengths.sum())
+    log(f"BF16 kv_build: {t_build:.2f} s ({tokens_total / t_build:.0f} tokens/s)")
+    result["kv_build_bf16_s"] = t_build
+    per_r = {}
+    bf16_out = {}
+    for r in wl.r_grid:
+        steps = args.steps if r == 1.0 else max(1, args.steps // 2)
+        ms, lg, dec = timed_eval(pool, r, hb, steps=steps, warmup=args.warmup)
+        per_r[str(r)] = {"bf16_bf16kv_tuples_per_s": n / (ms / 1e3), "ms": ms}
+        bf16_out[r] = (lg, dec)
+        log(f"BF16 r={r}: {ms:.1f} ms/step, {n / (ms / 1e3):.0f} tuples/s")
+    headline_ms = per_r["1.0"]["ms"]
+    # per-kernel timing inside one r = 1 op_eval
+    K.kvop_profile_start()
+    timed_eval(pool, 1.0, hb, steps=1)
+    prof = K.kvop_profile_stop()
+    log("profile (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in prof.items()})
+    K.kvop_pool_destroy(pool)
+    # ------------------------------------------------------------------ FP8 cache
+    if not args.no_fp8:
+        probe = K.kvop_pool_create(mb, K.KVOP_KV_FP8, 1 << 20)
+        need8 = sum(K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths)
+        K.kvop_pool_destroy(probe)
+        pool8 = K.kvop_pool_create(mb, K.KVOP_KV_FP8, need8 + (64 << 20))
+        h8, t8 = build(pool8, 0, n)
+        log(f"FP8 kv_build: {t8:.2f} s")
+        for r in wl.r_grid:
+            ms, lg, dec = timed_eval(pool8, r, h8, steps=max(1, args.steps // 2), warmup=args.warmup)
+            per_r[str(r)]["bf16_fp8kv_tuples_per_s"] = n / (ms / 1e3)
+            per_r[str(r)]["fp8kv_vs_bf16kv_decision_disagreement"] = float(np.mean(dec != bf16_out[r][1]))
+            log(f"FP8 r={r}: {ms:.1f} ms/step")
+        K.kvop_pool_destroy(pool8)
+    K.kvop_model_destroy(mb)
+    # ------------------------------------------------------------------ FP32 plain path (waves)
+    fp32 = None
+    if not args.no_fp32:
+        mf = K.kvop_model_create(cfg, flat, K.KVOP_F32)
+        probe = K.kvop_pool_create(mf, K.KVOP_KV_F32, 1 << 20)
+        sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
+        K.kvop_pool_destroy(probe)
+        cap = torch.cuda.mem_get_info()[0] - (24 << 30)
+        poolf = K.kvop_pool_create(mf, K.KVOP_KV_F32, cap)
+        ms_tot, t_build32, logits32, dec32 = 0.0, 0.0, [], []
+        a = 0
+        while a < n:
+            b, acc = a, 0
+            while b < n and acc + sizes[b] <= cap - (1 << 30):
+                acc += sizes[b]
+                b += 1
+            hf, tb = build(poolf, a, b)
+            t_build32 += tb
+            ms, lg, dec = timed_eval(poolf, 1.0, hf, sel=(a, b), steps=1, warmup=0)
+            ms_tot += ms
+            logits32.append(lg)
+            dec32.append(dec)
+            log(f"FP32 wave [{a}, {b}): build {tb:.1f} s, op_eval {ms:.1f} ms")
+            K.kvop_kv_release(poolf, hf)
+            a = b
+        K.kvop_pool_destroy(poolf)
+        K.kvop_model_destroy(mf)
+        dec32 = np.concatenate(dec32)
+        fp32 = {"tuples_per_s": n / (ms_tot / 1e3), "ms": ms_tot, "kv_build_s": t_build32,
+                "logits": np.concatenate(logits32), "dec": dec32}
+        log(f"FP32 plain: {fp32['tuples_per_s']:.0f} tuples/s")
+    del flat
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------------ CPU baseline: the oracle
+    cpu = oracle_baseline(shape, w, docs, wl.suffix, args.cpu_sample, bf16_out[1.0][0],
+                          None if fp32 is None else fp32["logits"])
+
+    # ------------------------------------------------------------------ roofline of the dominant kernel
+    gu_ms, gu_cnt = prof["gemm_gate_up"]
+    rows_main = n * 32
+    gu_flops = 2.0 * shape.d_model * 2 * shape.d_ffn * (rows_main * (shape.n_layers - 1) + n)
+    achieved = gu_flops / (gu_ms / 1e3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "gemm_gate_up (bf16, SwiGLU epilogue)", "achieved": achieved,
+                "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                "launches": gu_cnt, "avg_launch_ms": gu_ms / max(1, gu_cnt)}
+    att_ms, att_cnt = prof["attention"]
+    k1 = int(docs.lengths.sum())
+    att_bytes = (k1 + 32 * n) * 2 * shape.n_kv_heads * shape.head_dim * 2 * shape.n_layers
+    roof_att = {"bound": "hbm", "achieved": att_bytes / (att_ms / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": att_bytes / (att_ms / 1e3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": att_ms / max(1, att_cnt)}
+    value = n / (headline_ms / 1e3)
+    line = {
+        "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": headline_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "plain semantic filter at scale: 16-layer d2048 GQA decoder, 4096 docs "
+                               "lognormal(median 512, sigma 1) in [64,4096], 32-token suffix, r=1.0",
+                   "path": "bf16 weights/activations, bf16 KV cache (proxy stage not yet in the timed path)",
+                   "docs": n, "sum_L": k1},
+        "roofline": roofline,
+        "roofline_attention": roof_att,
+        "kernel_ms_per_step": {k: round(v[0], 3) for k, v in prof.items()},
+        "per_r": per_r,
+        "kv_build_bf16_s": result["kv_build_bf16_s"],
+        "cpu_baseline": cpu,
+    }
+    if fp32 is not None:
+        d16 = bf16_out[1.0][1]
+        lo32 = fp32["logits"][:, 0] - fp32["logits"][:, 1]
+        line["fp32_plain"] = {"tuples_per_s": fp32["tuples_per_s"], "ms": fp32["ms"],
+                              "kv_build_s": fp32["kv_build_s"],
+                              "bf16_vs_fp32_decision_disagreement": float(np.mean(d16 != fp32["dec"])),
+                              "bf16_vs_fp32_max_abs_logit_diff": float(np.max(np.abs(bf16_out[1.0][0] - fp32["logits"]))),
+                              "speedup_bf16_over_fp32": value / fp32["tuples_per_s"]}
+    print(json.dumps(line), flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(json.dumps(line) + "\n")
+
+
+def oracle_baseline(shape, w, docs, suffix, n_sample, gpu_bf16_logits, gpu_f32_logits):
+    """Time the FP64 oracle's filter evaluation (the suffix over cached rows) on the first
+    n_sample documents, after building their caches with the oracle (not timed)."""
+    from oracle import model as om
+    from paper_2602_04430_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    t0 = time.time()
+    m = om.Model(shape, w)
+    caches = []
+    for i in range(n_sample):
+        caches.append(om.kv_build(m, docs.doc(i)))
+        log(f"oracle kv_build doc {i} (L={docs.lengths[i]}) done at {time.time() - t0:.1f} s")
+    t_build = time.time() - t0
+    t1 = time.time()
+    res = []
+    for i in range(n_sample):
+        res.append(om.filter_eval(m, caches[i], np.arange(docs.lengths[i]), suffix, synth.YES_ID, synth.NO_ID))
+    t_eval = time.time() - t1
+    ref = np.stack([r.logits for r in res])
+    out = {"value": n_sample / t_eval, "unit": "tuples/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"FP64 NumPy oracle filter evaluation (r=1) of the first {n_sample} of the 4096 documents "
+                     f"(L={[int(x) for x in docs.lengths[:n_sample]]}), caches built by the oracle beforehand "
+                     f"({t_build:.1f} s, not in the rate)",
+           "seconds": t_eval,
+           "bf16_max_abs_logit_err_vs_oracle": float(np.max(np.abs(gpu_bf16_logits[:n_sample] - ref)))}
+    if gpu_f32_logits is not None:
+        out["fp32_max_abs_logit_err_vs_oracle"] = float(np.max(np.abs(gpu_f32_logits[:n_sample] - ref)))
+    log(f"oracle: {out['value']:.3f} tuples/s on {threads} threads")
+    return out
+
+
+if __name__ == "__main__":
+    main()

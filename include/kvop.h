@@ -168,7 +168,7 @@ kvop_status kvop_op_eval(kvop_pool* pool, const kvop_op* op, float r, const int3
 
 /* ---- diagnostics and tuning ------------------------------------------------
  * Run one projection C = A B^T with an explicit tile configuration `tile`
- * (0 .. kvop_gemm_num_tiles(dtype)-1).  dtype: KVOP_F32 or KVOP_BF16 operands;
+ * (0 .. kvop_gemm_num_tiles(dtype)-1, or -1 for the library's own choice).  dtype: KVOP_F32 or KVOP_BF16 operands;
  * epilogue 0 = store C in out_dtype, 1 = FP32 C += A B^T, 2 = SwiGLU over 16-row
  * interleaved gate/up rows of B (C has N/2 columns).  Device pointers; strides in
  * elements.  EINVAL when the tile cannot run the shape (K, lda, ldb must be
@@ -178,6 +178,14 @@ const char* kvop_gemm_tile_name(int32_t dtype, int32_t tile);
 kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epilogue, int32_t tile, const void* A,
                             const void* B, void* Cm, int32_t M, int32_t N, int32_t K, int64_t lda, int64_t ldb,
                             int64_t ldc, void* stream);
+/* Per-kernel-class timing of the library's own launches: while on, each launch of
+ * kvop_kv_build / kvop_op_eval is bracketed by HIP events on the caller's stream.
+ * kvop_profile_stop synchronises those events and writes, for class i < n, the summed
+ * milliseconds and the number of launches (classes named by kvop_profile_class_name). */
+kvop_status kvop_profile_start(void);
+kvop_status kvop_profile_stop(double* ms_out, int64_t* count_out, int32_t n);
+int32_t kvop_profile_num_classes(void);
+const char* kvop_profile_class_name(int32_t i);
 /* Record the best tile for (dtype, epilogue, N, K, M) in the library's tuning table
  * (used by later kvop_kv_build / kvop_op_eval calls). */
 kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epilogue, int32_t N, int32_t K, int32_t M, int32_t tile);

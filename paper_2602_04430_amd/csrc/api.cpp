@@ -39,6 +39,38 @@ constexpr int64_t kAlign = 256;
 
 int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// ---- optional per-kernel-class timing: HIP events recorded on the caller's stream around
+// each launch while profiling is on; read back (synchronising) by kvop_profile_stop.
+enum ProfClass { PC_GEMM_QKV, PC_GEMM_O, PC_GEMM_GATEUP, PC_GEMM_DOWN, PC_ATTENTION, PC_ROPE_KV, PC_RMSNORM,
+                 PC_EMBED, PC_HEAD, PC_OTHER, PC_COUNT };
+const char* kProfNames[PC_COUNT] = {"gemm_qkv", "gemm_o", "gemm_gate_up", "gemm_down", "attention", "rope_kv",
+                                    "rmsnorm", "embed", "head", "other"};
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[PC_COUNT] = {};
+  int64_t cnt[PC_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+Prof g_prof;
+struct ProfScope {
+  int k;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int k_, hipStream_t st_) : k(k_), st(st_) {
+    if (g_prof.on) { a = g_prof.get(); b = g_prof.get(); (void)hipEventRecord(a, st); }
+  }
+  ~ProfScope() {
+    if (a) { (void)hipEventRecord(b, st); g_prof.pending.push_back({k, {a, b}}); }
+  }
+};
+
 // Device buffer that grows on demand (synchronising the stream before a reallocation).
 struct DevBuf {
   void* p = nullptr;
@@ -261,17 +293,20 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   const int qc = m->qkv_cols();
   const int rows = lp.rows;
   const int dt = m->dt;
-  HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, rows, d, c.rms_eps, b.h, d, st));
+  { ProfScope ps(PC_RMSNORM, st); HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, rows, d, c.rms_eps, b.h, d, st)); }
   {
+    ProfScope ps(PC_GEMM_QKV, st);
     GemmShape s{rows, qc, d, d, d, qc};
     HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.qkv, s, st));
   }
   if (n_kvblocks > 0) {
+    ProfScope ps(PC_ROPE_KV, st);
     // prefill: rotate queries here; keys are rotated by the cache writer
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, 0, D, lp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
     HIPTRY(rope_write_kv(dt, kvdt, b.qkv, qc, kvblocks, n_kvblocks, H, Hkv, D, l, c.n_layers, m->cos_tab, m->sin_tab,
                          pool, st));
   } else {
+    ProfScope ps(PC_ROPE_KV, st);
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, Hkv, D, lp.pos, m->cos_tab, m->sin_tab, lp.alt_shift ? b.qalt : nullptr,
                    lp.alt_shift, st));
   }
@@ -299,22 +334,25 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   a.G = H / Hkv;
   a.pool = pool;
   a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
-  HIPTRY(attention(dt, kvdt, D, a, st));
+  { ProfScope ps(PC_ATTENTION, st); HIPTRY(attention(dt, kvdt, D, a, st)); }
   // rows continuing: all, or a strided selection (last row of each item)
   const int n = lp.n_sel;
   const int64_t sa = (int64_t)lp.sel_stride;
   const char* attn_sel = (const char*)b.attn + (int64_t)lp.sel_off * H * D * m->esz();
   float* x_sel = b.x + (int64_t)lp.sel_off * d;
   {
+    ProfScope ps(PC_GEMM_O, st);
     GemmShape s{n, d, H * D, sa * H * D, H * D, sa * d};
     HIPTRY(gemm(dt, DT_F32, EPI_ADD, gemm_pick_tile(dt, EPI_ADD, s), attn_sel, W.wo, x_sel, s, st));
   }
-  HIPTRY(rmsnorm_rows(dt, x_sel, sa * d, W.ffn_norm, n, d, c.rms_eps, b.h, d, st));
+  { ProfScope ps(PC_RMSNORM, st); HIPTRY(rmsnorm_rows(dt, x_sel, sa * d, W.ffn_norm, n, d, c.rms_eps, b.h, d, st)); }
   {
+    ProfScope ps(PC_GEMM_GATEUP, st);
     GemmShape s{n, 2 * F, d, d, d, F};
     HIPTRY(gemm(dt, dt, EPI_SWIGLU, gemm_pick_tile(dt, EPI_SWIGLU, s), b.h, W.wgu, b.act, s, st));
   }
   {
+    ProfScope ps(PC_GEMM_DOWN, st);
     GemmShape s{n, d, F, F, F, sa * d};
     HIPTRY(gemm(dt, DT_F32, EPI_ADD, gemm_pick_tile(dt, EPI_ADD, s), b.act, W.wdown, x_sel, s, st));
   }
@@ -869,7 +907,10 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
     char* ownbuf = (char*)m->ws.p + act;
     const int64_t own_ld = 2LL * Hkv * D;
 
-    HIPTRY(embed_suffix(m->dt, m->embed, (const int32_t*)(md + o_suf), S, (int)rows, d, c.vocab, bufs.x, st));
+    {
+      ProfScope ps(PC_EMBED, st);
+      HIPTRY(embed_suffix(m->dt, m->embed, (const int32_t*)(md + o_suf), S, (int)rows, d, c.vocab, bufs.x, st));
+    }
     LayerPlan lp{};
     lp.rows = (int)rows;
     lp.pos = (const int32_t*)(md + o_pos);
@@ -900,6 +941,7 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
     }
     const float* xlast = bufs.x + (int64_t)(S - 1) * d;
     if (kind != KVOP_MAP) {
+      ProfScope ps(PC_HEAD, st);
       HIPTRY(head_filter(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->yes_id, op->no_id,
                          op->theta_pos, op->theta_neg, logits + (int64_t)w0 * 2, decision ? decision + w0 : nullptr,
                          st));
@@ -999,6 +1041,37 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
   return KVOP_OK;
 }
 
+// ------------------------------------------------------------------ profiling
+kvop_status kvop_profile_start(void) {
+  g_prof.on = true;
+  for (int i = 0; i < PC_COUNT; i++) { g_prof.ms[i] = 0; g_prof.cnt[i] = 0; }
+  for (auto& pe : g_prof.pending) { g_prof.pool.push_back(pe.second.first); g_prof.pool.push_back(pe.second.second); }
+  g_prof.pending.clear();
+  return KVOP_OK;
+}
+
+kvop_status kvop_profile_stop(double* ms_out, int64_t* count_out, int32_t n) {
+  g_prof.on = false;
+  for (auto& pe : g_prof.pending) {
+    HIPTRY(hipEventSynchronize(pe.second.second));
+    float ms = 0.f;
+    HIPTRY(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+    g_prof.ms[pe.first] += ms;
+    g_prof.cnt[pe.first] += 1;
+    g_prof.pool.push_back(pe.second.first);
+    g_prof.pool.push_back(pe.second.second);
+  }
+  g_prof.pending.clear();
+  for (int i = 0; i < n && i < PC_COUNT; i++) {
+    if (ms_out) ms_out[i] = g_prof.ms[i];
+    if (count_out) count_out[i] = g_prof.cnt[i];
+  }
+  return KVOP_OK;
+}
+
+int32_t kvop_profile_num_classes(void) { return PC_COUNT; }
+const char* kvop_profile_class_name(int32_t i) { return i >= 0 && i < PC_COUNT ? kProfNames[i] : ""; }
+
 // ------------------------------------------------------------------ diagnostics / tuning
 int32_t kvop_gemm_num_tiles(int32_t dtype) { return gemm_num_tiles(dtype == KVOP_F32 ? DT_F32 : DT_BF16); }
 
@@ -1017,6 +1090,7 @@ kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epi, int32
   int odt = out_dtype == KVOP_F32 ? DT_F32 : DT_BF16;
   if (dt == DT_F32 && odt != DT_F32) return fail(KVOP_EINVAL, "f32 operands produce f32 results");
   GemmShape s{M, N, K, lda, ldb, ldc};
+  if (tile < 0) tile = gemm_pick_tile(dt, epi, s);
   if (!gemm_tile_ok(dt, tile, s, epi)) return fail(KVOP_EINVAL, "tile cannot run this shape");
   HIPTRY(gemm(dt, odt, epi, tile, A, B, Cm, s, (hipStream_t)stream));
   return KVOP_OK;

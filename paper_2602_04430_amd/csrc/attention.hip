@@ -237,7 +237,7 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(AttnArgs a) {
             u32x4 kf = *reinterpret_cast<const u32x4*>(krow + 16 * k + 4 * g4);
 #pragma unroll
             for (int t = 0; t < 4; t++)
-              s[b] = mfma_f32(__builtin_bit_cast(float, kf[t]), __builtin_bit_cast(float, qf[k][t]), s[b]);
+              s[b] = mfma_f32(as_f32(kf[t]), as_f32(qf[k][t]), s[b]);
           } else {
             u32x4 kf = *reinterpret_cast<const u32x4*>(krow + 32 * k + 8 * g4);
             s[b] = mfma_bf16(__builtin_bit_cast(u16x8, kf), __builtin_bit_cast(u16x8, qf[k]), s[b]);

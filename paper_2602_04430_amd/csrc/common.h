@@ -61,6 +61,10 @@ __device__ inline uint32_t f32_to_e4m3(float x) {
   return code | sign;
 }
 
+// Reinterpret a 32-bit lane value as float.  Takes the value by copy: a bit_cast applied
+// directly to an ext-vector element subscript reads element 0 of the vector.
+__device__ inline float as_f32(uint32_t v) { return __builtin_bit_cast(float, v); }
+
 __device__ inline float silu(float x) { return x / (1.0f + __expf(-x)); }
 
 // wavefront reductions (64 lanes)

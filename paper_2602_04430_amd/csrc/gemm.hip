@@ -115,8 +115,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
           for (int i = 0; i < MI; i++)
 #pragma unroll
             for (int j = 0; j < NI; j++)
-              acc[i][j] = mfma_f32(__builtin_bit_cast(float, af[i][t]), __builtin_bit_cast(float, bfr[j][t]),
-                                   acc[i][j]);
+              acc[i][j] = mfma_f32(as_f32(af[i][t]), as_f32(bfr[j][t]), acc[i][j]);
       } else {
 #pragma unroll
         for (int i = 0; i < MI; i++)

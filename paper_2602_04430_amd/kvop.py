@@ -62,6 +62,10 @@ _SIGS = {
                                   C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P]),
     "kvop_gemm_set_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "kvop_debug_read_cache": (C.c_int, [_P, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "kvop_profile_start": (C.c_int, []),
+    "kvop_profile_stop": (C.c_int, [_P, _P, C.c_int32]),
+    "kvop_profile_num_classes": (C.c_int32, []),
+    "kvop_profile_class_name": (C.c_char_p, [C.c_int32]),
 }
 _lib_handle = None
 
@@ -198,3 +202,24 @@ def kvop_gemm_set_tile(dtype: int, epilogue: int, N: int, K: int, M: int, tile: 
 def kvop_debug_read_cache(pool, handle, layer: int, kv_head: int, kv: int, out_dev, stream=None) -> None:
     _check(lib().kvop_debug_read_cache(pool, C.c_uint64(int(handle)), layer, kv_head, kv, _dptr(out_dev),
                                        _stream(stream)))
+
+
+def kvop_profile_start() -> None:
+    _check(lib().kvop_profile_start())
+
+
+def kvop_profile_stop() -> dict:
+    """{class name: (milliseconds, launches)} since kvop_profile_start (synchronises)."""
+    n = int(lib().kvop_profile_num_classes())
+    ms = np.zeros(n, np.float64)
+    cnt = np.zeros(n, np.int64)
+    _check(lib().kvop_profile_stop(ms.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p), n))
+    return {lib().kvop_profile_class_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def kvop_profile_num_classes() -> int:
+    return int(lib().kvop_profile_num_classes())
+
+
+def kvop_profile_class_name(i: int) -> str:
+    return lib().kvop_profile_class_name(i).decode()

@@ -174,3 +174,103 @@ def test_error_paths(device):
     assert status(lambda: eng.build(big)) == K.KVOP_ENOMEM
     assert K.kvop_pool_stats(eng.pool) == u0                                                   # nothing leaked
     eng.close()
+
+
+# ----------------------------------------------------------------------------- map and join
+
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
+def test_map_greedy_decode_matches_oracle(device, compute, kv):
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 8, gain_jitter=0.1)
+    docs = synth.make_docs_uniform(10, 1, 90, shape.vocab, seed=8)
+    suffix = synth.suffix_tokens(12, shape.vocab, seed=8)
+    lo, nsl, n_gen = 256, 256, 8
+    eng = Engine(shape, w, compute, kv)
+    handles = eng.build(docs)
+    r = 0.5
+    idx, offs = synth.retained_lists(docs.lengths, r, seed=8)
+    say("map", compute, kv)
+    lg, tk = eng.map(handles, idx, offs, suffix, lo, nsl, n_gen, r=r)
+    m = om.Model(shape, w)
+    E = BOUND[(compute, kv)]
+    out_of_band = 0
+    for i in range(len(docs.lengths)):
+        res = om.map_eval(m, om.kv_build(m, docs.doc(i)), idx[offs[i]:offs[i + 1]], suffix, lo, nsl, n_gen)
+        srt = np.sort(res.step_logits, axis=1)
+        margins = srt[:, -1] - srt[:, -2]
+        for t in range(n_gen):
+            if not np.array_equal(tk[i, :t], res.tokens[:t]):
+                break                                   # the texts diverged inside the band earlier
+            assert np.max(np.abs(lg[i, t] - res.step_logits[t])) <= E, (i, t)
+        if np.all(margins >= 2 * E):
+            out_of_band += 1
+            np.testing.assert_array_equal(tk[i], res.tokens)
+    if compute == "f32":
+        assert out_of_band == len(docs.lengths)
+    eng.close()
+
+
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
+def test_join_pairs_match_oracle(device, compute, kv):
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 9, gain_jitter=0.1)
+    docs = synth.make_docs_uniform(8, 1, 100, shape.vocab, seed=9)
+    suffix = synth.suffix_tokens(17, shape.vocab, seed=9)
+    pairs = synth.join_pairs(8, 12, seed=9)
+    eng = Engine(shape, w, compute, kv)
+    handles = eng.build(docs)
+    r = 0.5
+    idx1, offs1 = synth.retained_lists(docs.lengths, r, seed=9)
+    lists = [idx1[offs1[i]:offs1[i + 1]] for i in range(8)]
+    idx, offs, hs = [], [0], []
+    for a, b in pairs:
+        for x in (a, b):
+            idx.append(lists[x])
+            offs.append(offs[-1] + len(lists[x]))
+            hs.append(handles[x])
+    idx = np.concatenate(idx)
+    say("join", compute, kv)
+    lg, dec = eng.filter(np.array(hs, np.uint64), idx, np.array(offs), suffix, r=r, kind=K.KVOP_JOIN)
+    m = om.Model(shape, w)
+    caches = [om.kv_build(m, docs.doc(i)) for i in range(8)]
+    E = BOUND[(compute, kv)]
+    lo_ref = []
+    for p, (a, b) in enumerate(pairs):
+        res = om.join_eval(m, caches[a], lists[a], caches[b], lists[b], suffix, synth.YES_ID, synth.NO_ID)
+        assert np.max(np.abs(lg[p] - res.logits)) <= E, (p, np.max(np.abs(lg[p] - res.logits)))
+        lo_ref.append(res.log_odds)
+    assert decisions_agree_outside_band(lo_ref, dec, E)[0] == 0
+    eng.close()
+
+
+# ----------------------------------------------------------------------------- invariances
+
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "fp8")])
+def test_permutation_and_batch_split_invariance(device, compute, kv):
+    """Results of an item do not depend on the other items of the call or their order."""
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 10)
+    docs = synth.make_docs_uniform(40, 1, 120, shape.vocab, seed=10)
+    suffix = synth.suffix_tokens(9, shape.vocab, seed=10)
+    eng = Engine(shape, w, compute, kv)
+    handles = eng.build(docs)
+    r = 0.25
+    idx, offs = synth.retained_lists(docs.lengths, r, seed=10)
+    lg, dec = eng.filter(handles, idx, offs, suffix, r=r)
+    perm = np.random.default_rng(10).permutation(40)
+    lists = [idx[offs[i]:offs[i + 1]] for i in range(40)]
+    pidx = np.concatenate([lists[i] for i in perm])
+    poffs = np.concatenate([[0], np.cumsum([len(lists[i]) for i in perm])])
+    lg2, dec2 = eng.filter(handles[perm], pidx, poffs, suffix, r=r)
+    np.testing.assert_array_equal(lg2, lg[perm])
+    np.testing.assert_array_equal(dec2, dec[perm])
+    # split into two calls
+    h1 = eng.filter(handles[:13], idx[:offs[13]], offs[:14], suffix, r=r)
+    h2 = eng.filter(handles[13:], idx[offs[13]:], offs[13:] - offs[13], suffix, r=r)
+    np.testing.assert_array_equal(np.concatenate([h1[0], h2[0]]), lg)
+    # an explicit full list at r = 1 is the r = 1 path
+    fidx, foffs = synth.full_lists(docs.lengths)
+    a = eng.filter(handles, fidx, foffs, suffix, r=1.0)
+    b = eng.filter(handles, fidx, foffs, suffix, r=0.999, flags=K.KVOP_FLAG_ANY_COUNT)
+    np.testing.assert_array_equal(a[0], b[0])
+    eng.close()
