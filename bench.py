@@ -159,7 +159,7 @@ def main():
         probe = K.kvop_pool_create(mf, K.KVOP_KV_F32, 1 << 20)
         sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
         K.kvop_pool_destroy(probe)
-        cap = torch.cuda.mem_get_info()[0] - (24 << 30)
+        cap = min(torch.cuda.mem_get_info()[0] - (24 << 30), sum(sizes) + (2 << 30))
         poolf = K.kvop_pool_create(mf, K.KVOP_KV_F32, cap)
         ms_tot, t_build32, logits32, dec32 = 0.0, 0.0, [], []
         a = 0
