@@ -1,9 +1,9 @@
 // Grouped-query attention of a block of query rows over gathered cached rows plus the
 // item's own (suffix / generated) rows, with an online softmax in FP32.
 //
-// One workgroup = one work item x one kv head.  Its query rows are the G query heads of
-// that kv head times up to Pmax positions (row r -> head r / Pmax, position r % Pmax);
-// each wavefront owns 16 of them.  Keys stream through LDS in tiles of KT rows taken, in
+// One workgroup (4 wavefronts) = one work item x one kv head.  Its query rows are the G
+// query heads of that kv head times up to Pmax positions (row r -> head r / Pmax, position
+// r % Pmax); each wavefront owns 16 of them (wavefronts without rows only help staging).  Keys stream through LDS in tiles of KT rows taken, in
 // order, from: document A's cached rows (contiguous or through a retained-row index list),
 // document B's cached rows (joins: positions shifted by L_A; the matching queries are
 // rotated at position - L_A), and the own rows.  A key is visible to a query iff its
@@ -35,134 +35,173 @@ struct AttnCfg {
   static constexpr int VS_ELEMS = F32 ? KT * KLD : D * VTLD;
 };
 
-// Stage one tile of keys (rows t0 .. t0+KT-1 of a source) into LDS.
-//   src_k/src_v : element pointers of row 0 of the source (row pitch `pitch` elements)
-//   idx         : retained-row list of the source or null (then row = t0 + j)
-//   n           : rows in the source; rows past n are marked invisible
-//   clampL      : rows are clamped to [0, clampL) as a guard against bad lists
-//   pos_add     : key position = row + pos_add
-//   ksc/vsc     : FP8 block scales of the source (per 16 rows) or null
-template <typename TC, typename TS, int D, int NT>
-__device__ inline void stage_tile(TC* __restrict__ Ks, TC* __restrict__ Vs, float* ksc_s, float* vsc_s,
-                                  int* kpos_s, const TS* __restrict__ src_k, const TS* __restrict__ src_v,
-                                  int64_t pitch, const int32_t* __restrict__ idx, int t0, int n, int clampL,
-                                  int pos_add, const float* __restrict__ ksc, const float* __restrict__ vsc) {
+// One key source of a work item: rows of a cached document (through an optional retained
+// list) or the item's own rows.  All threads of the workgroup hold the same description.
+struct KeySrc {
+  const uint8_t* k;      // row 0 of the keys
+  const uint8_t* v;      // row 0 of the values
+  int64_t pitch;         // bytes between consecutive rows
+  const int32_t* idx;    // retained-row list or null (rows 0..n-1)
+  const float* ksc;      // FP8 block scales (per 16 rows) or null
+  const float* vsc;
+  int n, clampL, pos_add;
+  bool cache;            // cache dtype (else compute dtype)
+};
+
+// Register-staged tile of KT keys: each thread fetches its share of 16-byte chunks from
+// global memory (fetch), then writes them to LDS, widening FP8 and transposing V for the
+// BF16 path (commit).  The fetch of tile i+1 is issued before the compute of tile i.
+template <typename TC, typename TKV, int D>
+struct TileStage {
   using C = AttnCfg<TC, D>;
-  constexpr int KT = C::KT;
-  const int tid = threadIdx.x;
-  // row ids, positions and scales of this tile
-  for (int j = tid; j < KT; j += NT) {
-    int t = t0 + j;
-    int row = 0, pos = 0x7fffffff;
-    float ks = 1.f, vs = 1.f;
-    if (t < n) {
-      row = idx ? idx[t] : t;
-      row = min(max(row, 0), clampL - 1);
-      pos = row + pos_add;
-      if (ksc) { ks = ksc[row >> 4]; vs = vsc[row >> 4]; }
-    }
-    kpos_s[j] = pos;
-    ksc_s[j] = ks;
-    vsc_s[j] = vs;
+  static constexpr int KT = C::KT;
+  static constexpr int NT = 256;
+  static constexpr int CPR = D * (int)sizeof(TC) / 16;           // chunks per row in the compute dtype
+  static constexpr int NK = (KT * CPR + NT - 1) / NT;             // K chunks per thread
+  static constexpr int NVU = C::F32 ? NK : ((KT / 2) * CPR + NT - 1) / NT;  // V units per thread
+  u32x4 kr[NK];
+  u32x4 vr0[NVU], vr1[NVU];
+  int kpos[NK];
+  float ks[NK], vs[NK];
+  bool fp8;                                                      // this tile came from an FP8 source
+
+  __device__ static int row_of(const KeySrc& s, int t) {
+    int row = s.idx ? s.idx[t] : t;
+    return min(max(row, 0), s.clampL - 1);
   }
-  __syncthreads();
-  constexpr int CPR = D * (int)sizeof(TS) / 16;  // 16-byte chunks per source row
-  if constexpr (C::F32) {
-    // f32 source into row-major K and V tiles
-    for (int c = tid; c < KT * CPR; c += NT) {
-      int j = c / CPR, cc = c % CPR;
-      int t = t0 + j;
-      u32x4 kv = {0, 0, 0, 0}, vv = {0, 0, 0, 0};
-      if (t < n) {
-        int row = kpos_s[j] - pos_add;
-        kv = *reinterpret_cast<const u32x4*>(src_k + row * pitch + cc * 4);
-        vv = *reinterpret_cast<const u32x4*>(src_v + row * pitch + cc * 4);
-      }
-      *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 4) = kv;
-      *reinterpret_cast<u32x4*>(Vs + j * C::KLD + cc * 4) = vv;
-    }
-  } else {
-    // K: row-major bf16
-    for (int c = tid; c < KT * CPR; c += NT) {
-      int j = c / CPR, cc = c % CPR;
-      int t = t0 + j;
-      u32x4 raw = {0, 0, 0, 0};
-      if (t < n) {
-        int row = kpos_s[j] - pos_add;
-        raw = *reinterpret_cast<const u32x4*>(reinterpret_cast<const uint8_t*>(src_k + row * pitch) + cc * 16);
-      }
-      if constexpr (sizeof(TS) == 2) {
-        *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 8) = raw;
-      } else {  // 16 E4M3 codes -> 16 bf16
-        u32x4 lo, hi;
+
+  __device__ void fetch(const KeySrc& s, int t0) {
+    const int tid = threadIdx.x;
+    fp8 = (sizeof(TKV) == 1) && s.cache;
+    // an FP8 row is half as many 16-byte chunks; the widened K chunk covers 16 elements
+    const int cpr_src = fp8 ? CPR / 2 : CPR;
 #pragma unroll
-        for (int w = 0; w < 4; w++) {
-          uint32_t x = raw[w];
-          uint32_t b0 = e4m3_to_bf16(x & 0xff), b1 = e4m3_to_bf16((x >> 8) & 0xff);
-          uint32_t b2 = e4m3_to_bf16((x >> 16) & 0xff), b3 = e4m3_to_bf16(x >> 24);
-          if (w < 2) { lo[2 * w] = b0 | (b1 << 16); lo[2 * w + 1] = b2 | (b3 << 16); }
-          else { hi[2 * (w - 2)] = b0 | (b1 << 16); hi[2 * (w - 2) + 1] = b2 | (b3 << 16); }
+    for (int i = 0; i < NK; i++) {
+      int c = tid + i * NT;
+      int j = c / CPR, cc = c % CPR;
+      int t = t0 + j;
+      kr[i] = u32x4{0, 0, 0, 0};
+      kpos[i] = 0x7fffffff;
+      ks[i] = 1.f;
+      vs[i] = 1.f;
+      if (c < KT * CPR && t < s.n) {
+        int row = row_of(s, t);
+        kpos[i] = row + s.pos_add;
+        if (fp8) {
+          ks[i] = s.ksc[row >> 4];
+          vs[i] = s.vsc[row >> 4];
         }
-        *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 16) = lo;
-        *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 16 + 8) = hi;
+        if (cc < cpr_src) kr[i] = *reinterpret_cast<const u32x4*>(s.k + row * s.pitch + cc * 16);
+        if constexpr (C::F32) vr0[i] = *reinterpret_cast<const u32x4*>(s.v + row * s.pitch + cc * 16);
+      } else if constexpr (C::F32) {
+        vr0[i] = u32x4{0, 0, 0, 0};
       }
     }
-    // V: transposed bf16, two keys per thread so that each LDS write is a packed dword
-    constexpr int EPC = 16 / (int)sizeof(TS);     // elements per chunk
-    for (int c = tid; c < (KT / 2) * CPR; c += NT) {
-      int jp = c / CPR, cc = c % CPR;
-      int j0 = 2 * jp;
-      u32x4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
-      if (t0 + j0 < n) {
-        int row = kpos_s[j0] - pos_add;
-        r0 = *reinterpret_cast<const u32x4*>(reinterpret_cast<const uint8_t*>(src_v + row * pitch) + cc * 16);
+    if constexpr (!C::F32) {
+#pragma unroll
+      for (int i = 0; i < NVU; i++) {
+        int u = tid + i * NT;
+        int jp = u / CPR, cc = u % CPR;
+        int t = t0 + 2 * jp;
+        vr0[i] = u32x4{0, 0, 0, 0};
+        vr1[i] = u32x4{0, 0, 0, 0};
+        if (u < (KT / 2) * CPR && cc < cpr_src) {
+          if (t < s.n) vr0[i] = *reinterpret_cast<const u32x4*>(s.v + row_of(s, t) * s.pitch + cc * 16);
+          if (t + 1 < s.n) vr1[i] = *reinterpret_cast<const u32x4*>(s.v + row_of(s, t + 1) * s.pitch + cc * 16);
+        }
       }
-      if (t0 + j0 + 1 < n) {
-        int row = kpos_s[j0 + 1] - pos_add;
-        r1 = *reinterpret_cast<const u32x4*>(reinterpret_cast<const uint8_t*>(src_v + row * pitch) + cc * 16);
+    }
+  }
+
+  __device__ void commit(TC* __restrict__ Ks, TC* __restrict__ Vs, float* ksc_s, float* vsc_s, int* kpos_s) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NK; i++) {
+      int c = tid + i * NT;
+      int j = c / CPR, cc = c % CPR;
+      if (c >= KT * CPR) continue;
+      if (cc == 0) {
+        kpos_s[j] = kpos[i];
+        ksc_s[j] = ks[i];
+        vsc_s[j] = vs[i];
       }
+      if constexpr (C::F32) {
+        *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 4) = kr[i];
+        *reinterpret_cast<u32x4*>(Vs + j * C::KLD + cc * 4) = vr0[i];
+      } else {
+        if (!fp8) {
+          *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 8) = kr[i];
+        } else if (cc < CPR / 2) {  // 16 codes -> 16 bf16 (elements 16 cc .. 16 cc + 15)
+          u32x4 lo, hi;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            uint32_t x = kr[i][q];
+            uint32_t b0 = e4m3_to_bf16(x & 0xff), b1 = e4m3_to_bf16((x >> 8) & 0xff);
+            uint32_t b2 = e4m3_to_bf16((x >> 16) & 0xff), b3 = e4m3_to_bf16(x >> 24);
+            if (q < 2) { lo[2 * q] = b0 | (b1 << 16); lo[2 * q + 1] = b2 | (b3 << 16); }
+            else { hi[2 * (q - 2)] = b0 | (b1 << 16); hi[2 * (q - 2) + 1] = b2 | (b3 << 16); }
+          }
+          *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 16) = lo;
+          *reinterpret_cast<u32x4*>(Ks + j * C::KLD + cc * 16 + 8) = hi;
+        }
+      }
+    }
+    if constexpr (!C::F32) {
       uint32_t* vt = reinterpret_cast<uint32_t*>(Vs);
 #pragma unroll
-      for (int e = 0; e < EPC; e++) {
-        uint32_t a, b;
-        if constexpr (sizeof(TS) == 2) {
-          a = (r0[e >> 1] >> ((e & 1) * 16)) & 0xffff;
-          b = (r1[e >> 1] >> ((e & 1) * 16)) & 0xffff;
-        } else {
-          a = e4m3_to_bf16((r0[e >> 2] >> ((e & 3) * 8)) & 0xff);
-          b = e4m3_to_bf16((r1[e >> 2] >> ((e & 3) * 8)) & 0xff);
+      for (int i = 0; i < NVU; i++) {
+        int u = tid + i * NT;
+        int jp = u / CPR, cc = u % CPR;
+        if (u >= (KT / 2) * CPR) continue;
+        int j0 = 2 * jp;
+        if (!fp8) {
+#pragma unroll
+          for (int e = 0; e < 8; e++) {
+            uint32_t a = (vr0[i][e >> 1] >> ((e & 1) * 16)) & 0xffff;
+            uint32_t b = (vr1[i][e >> 1] >> ((e & 1) * 16)) & 0xffff;
+            vt[((cc * 8 + e) * C::VTLD + j0) >> 1] = a | (b << 16);
+          }
+        } else if (cc < CPR / 2) {
+#pragma unroll
+          for (int e = 0; e < 16; e++) {
+            uint32_t a = e4m3_to_bf16((vr0[i][e >> 2] >> ((e & 3) * 8)) & 0xff);
+            uint32_t b = e4m3_to_bf16((vr1[i][e >> 2] >> ((e & 3) * 8)) & 0xff);
+            vt[((cc * 16 + e) * C::VTLD + j0) >> 1] = a | (b << 16);
+          }
         }
-        int d = cc * EPC + e;
-        vt[(d * C::VTLD + j0) >> 1] = a | (b << 16);
       }
     }
   }
-}
+};
 
-template <typename TC, typename TKV, int D, int NW>
-__global__ __launch_bounds__(NW * 64) void attn_kernel(AttnArgs a) {
+template <typename TC, typename TKV, int D>
+__global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
   using C = AttnCfg<TC, D>;
   constexpr int KT = C::KT;
-  constexpr int NT = NW * 64;
   constexpr int NB = KT / 16;                    // 16-key blocks per tile
   constexpr int ND = D / 16;                     // 16-wide d blocks of the output
+  constexpr bool FP8 = sizeof(TKV) == 1;
   __shared__ __attribute__((aligned(16))) TC Ks[C::KS_ELEMS];
   __shared__ __attribute__((aligned(16))) TC Vs[C::VS_ELEMS];
   __shared__ float ksc_s[KT], vsc_s[KT];
   __shared__ int kpos_s[KT];
 
-  const AttnWork w = a.work[blockIdx.x];
-  const int h = blockIdx.y;
+  // kv head fastest: consecutive workgroups are the heads of one item, so the longest-first
+  // order of the work list holds across heads
+  const int Hkv = a.Hkv;
+  const int h = blockIdx.x % Hkv;
+  const AttnWork w = a.work[blockIdx.x / Hkv];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int qi = lane & 15, g4 = lane >> 4;
   const int r = wave * 16 + qi;
   const int gq = r / a.Pmax, p = r % a.Pmax;
   const bool qvalid = gq < a.G && p < w.n_q;
+  const bool wave_active = __any(qvalid);
   const int hq = h * a.G + (gq < a.G ? gq : 0);
   const int qpos = w.q_pos0 + p;
   const int64_t qrow = (int64_t)w.q_row0 + (qvalid ? p : 0);
 
-  // ---- query fragments (B operand of S^T = K Q^T)
+  // ---- query fragments (B operand of S^T = K Q^T); qa: rotated for document B (joins)
   constexpr int NQ = C::F32 ? D / 16 : D / 32;
   u32x4 qf[NQ], qa[NQ];
   const bool has_b = w.n_b > 0;
@@ -177,19 +216,73 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(AttnArgs a) {
     }
   }
 
+  // ---- key sources: 0 = document A, 1 = document B, 2 = own rows
+  KeySrc src[3];
+#pragma unroll
+  for (int sidx = 0; sidx < 2; sidx++) {
+    KeySrc& s = src[sidx];
+    int64_t off = sidx == 0 ? w.off_a : w.off_b;
+    int L = sidx == 0 ? w.L_a : w.L_b;
+    int64_t il = sidx == 0 ? w.idx_a : w.idx_b;
+    s.n = sidx == 0 ? w.n_a : w.n_b;
+    s.cache = true;
+    s.clampL = max(L, 1);
+    s.pos_add = sidx == 1 ? w.L_a : 0;
+    s.idx = il >= 0 ? a.idx + il : nullptr;
+    s.ksc = s.vsc = nullptr;
+    s.pitch = (int64_t)D * (int64_t)sizeof(TKV);
+    if (s.n > 0) {
+      const uint8_t* base = a.pool + off;
+      const int64_t kv_elems = (int64_t)L * D;
+      const int64_t head_off = ((int64_t)(a.layer * Hkv + h) * 2) * kv_elems;
+      s.k = base + head_off * (int64_t)sizeof(TKV);
+      s.v = s.k + kv_elems * (int64_t)sizeof(TKV);
+      if constexpr (FP8) {
+        int nblk = (L + 15) >> 4;
+        const float* sb = reinterpret_cast<const float*>(base + (int64_t)2 * a.n_layers * Hkv * kv_elems);
+        s.ksc = sb + ((int64_t)(a.layer * Hkv + h) * 2) * nblk;
+        s.vsc = s.ksc + nblk;
+      }
+    } else {
+      s.k = s.v = a.pool;
+    }
+  }
+  {
+    KeySrc& s = src[2];
+    s.n = w.n_own;
+    s.cache = false;
+    s.clampL = max(w.n_own, 1);
+    s.pos_add = w.own_pos0;
+    s.idx = nullptr;
+    s.ksc = s.vsc = nullptr;
+    s.pitch = a.own_stride * (int64_t)sizeof(TC);
+    const uint8_t* ob = reinterpret_cast<const uint8_t*>(a.own) + (int64_t)w.own_row0 * s.pitch;
+    s.k = ob + (int64_t)(a.own_kcol + h * D) * (int64_t)sizeof(TC);
+    s.v = ob + (int64_t)(a.own_vcol + h * D) * (int64_t)sizeof(TC);
+  }
+  const int TA = (src[0].n + KT - 1) / KT, TB = (src[1].n + KT - 1) / KT, TO = (src[2].n + KT - 1) / KT;
+  const int T = TA + TB + TO;
+
   float m_run = -INFINITY, l_run = 0.f;
   f32x4 o[ND];
 #pragma unroll
   for (int i = 0; i < ND; i++) o[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int Hkv = a.Hkv;
-  constexpr bool FP8 = sizeof(TKV) == 1;
-  // three key sources: 0 = document A, 1 = document B, 2 = own rows
-  for (int src = 0; src < 3; src++) {
-    int n = src == 0 ? w.n_a : (src == 1 ? w.n_b : w.n_own);
-    // document B is scored with the queries rotated at (position - L_A): swap them in for
-    // source 1 and back afterwards (register moves; no dynamically indexed arrays)
-    if (src >= 1 && has_b) {
+  TileStage<TC, TKV, D> stage;
+  auto fetch_tile = [&](int ti) {
+    if (ti < TA) stage.fetch(src[0], ti * KT);
+    else if (ti < TA + TB) stage.fetch(src[1], (ti - TA) * KT);
+    else stage.fetch(src[2], (ti - TA - TB) * KT);
+  };
+  if (T > 0) fetch_tile(0);
+  for (int ti = 0; ti < T; ti++) {
+    __syncthreads();  // the previous tile is fully consumed
+    stage.commit(Ks, Vs, ksc_s, vsc_s, kpos_s);
+    const bool tile_fp8 = stage.fp8;
+    __syncthreads();
+    if (ti + 1 < T) fetch_tile(ti + 1);  // in flight during this tile's compute
+    // document B is scored with the queries rotated at (position - L_A)
+    if (has_b && (ti == TA || ti == TA + TB)) {
 #pragma unroll
       for (int k = 0; k < NQ; k++) {
         u32x4 tmp = qf[k];
@@ -197,117 +290,89 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(AttnArgs a) {
         qa[k] = tmp;
       }
     }
-    if (n <= 0) continue;
-    for (int t0 = 0; t0 < n; t0 += KT) {
-      __syncthreads();  // previous tile fully consumed
-      if (src < 2) {
-        int64_t off = src == 0 ? w.off_a : w.off_b;
-        int L = src == 0 ? w.L_a : w.L_b;
-        int64_t il = src == 0 ? w.idx_a : w.idx_b;
-        const uint8_t* base = a.pool + off;
-        int64_t kv_elems = (int64_t)L * D;
-        int64_t head_off = ((int64_t)(a.layer * Hkv + h) * 2) * kv_elems;  // elements
-        const TKV* kp = reinterpret_cast<const TKV*>(base) + head_off;
-        const TKV* vp = kp + kv_elems;
-        const float *ks = nullptr, *vs = nullptr;
-        if constexpr (FP8) {
-          int nblk = (L + 15) >> 4;
-          const float* sb = reinterpret_cast<const float*>(base + (int64_t)2 * a.n_layers * Hkv * kv_elems);
-          ks = sb + ((int64_t)(a.layer * Hkv + h) * 2) * nblk;
-          vs = ks + nblk;
-        }
-        stage_tile<TC, TKV, D, NT>(Ks, Vs, ksc_s, vsc_s, kpos_s, kp, vp, D, il >= 0 ? a.idx + il : nullptr, t0, n, L,
-                                   src == 1 ? w.L_a : 0, ks, vs);
-      } else {
-        const TC* ob = reinterpret_cast<const TC*>(a.own) + (int64_t)w.own_row0 * a.own_stride;
-        stage_tile<TC, TC, D, NT>(Ks, Vs, ksc_s, vsc_s, kpos_s, ob + a.own_kcol + h * D, ob + a.own_vcol + h * D,
-                                  a.own_stride, nullptr, t0, n, n, w.own_pos0, nullptr, nullptr);
-      }
-      __syncthreads();
+    if (!wave_active) continue;
 
-      // ---- scores S^T[key][query]: lane holds keys 16*b + 4*g4 + t of query column qi
-      f32x4 s[NB];
+    // ---- scores S^T[key][query]: lane holds keys 16*b + 4*g4 + t of query column qi
+    f32x4 s[NB];
 #pragma unroll
-      for (int b = 0; b < NB; b++) {
-        s[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const TC* krow = Ks + (16 * b + qi) * C::KLD;
+    for (int b = 0; b < NB; b++) {
+      s[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      const TC* krow = Ks + (16 * b + qi) * C::KLD;
 #pragma unroll
-        for (int k = 0; k < NQ; k++) {
-          if constexpr (C::F32) {
-            u32x4 kf = *reinterpret_cast<const u32x4*>(krow + 16 * k + 4 * g4);
+      for (int k = 0; k < NQ; k++) {
+        if constexpr (C::F32) {
+          u32x4 kf = *reinterpret_cast<const u32x4*>(krow + 16 * k + 4 * g4);
 #pragma unroll
-            for (int t = 0; t < 4; t++)
-              s[b] = mfma_f32(as_f32(kf[t]), as_f32(qf[k][t]), s[b]);
-          } else {
-            u32x4 kf = *reinterpret_cast<const u32x4*>(krow + 32 * k + 8 * g4);
-            s[b] = mfma_bf16(__builtin_bit_cast(u16x8, kf), __builtin_bit_cast(u16x8, qf[k]), s[b]);
-          }
+          for (int t = 0; t < 4; t++) s[b] = mfma_f32(as_f32(kf[t]), as_f32(qf[k][t]), s[b]);
+        } else {
+          u32x4 kf = *reinterpret_cast<const u32x4*>(krow + 32 * k + 8 * g4);
+          s[b] = mfma_bf16(__builtin_bit_cast(u16x8, kf), __builtin_bit_cast(u16x8, qf[k]), s[b]);
         }
       }
-      // ---- mask, scale, online softmax (statistics in FP32)
-      float mx = -INFINITY;
+    }
+    // ---- mask, scale, online softmax (statistics in FP32)
+    float mx = -INFINITY;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        int key = 16 * b + 4 * g4 + t;
+        bool vis = qvalid && kpos_s[key] <= qpos;
+        float v = s[b][t] * a.scale_log2;
+        if (FP8 && tile_fp8) v *= ksc_s[key];
+        v = vis ? v : -INFINITY;
+        s[b][t] = v;
+        mx = fmaxf(mx, v);
+      }
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    const float m_new = fmaxf(m_run, mx);
+    const float alpha = (m_new == -INFINITY) ? 1.f : exp2f(m_run - m_new);
+    float psum = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        float pv = (s[b][t] == -INFINITY) ? 0.f : exp2f(s[b][t] - m_new);
+        s[b][t] = pv;
+        psum += pv;
+      }
+    l_run = l_run * alpha + psum;
+    m_run = m_new;
+#pragma unroll
+    for (int i = 0; i < ND; i++) o[i] *= alpha;
+
+    // ---- O^T[d][query] += V^T[d][key] P^T[key][query]
+    if constexpr (C::F32) {
 #pragma unroll
       for (int b = 0; b < NB; b++)
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-          int key = 16 * b + 4 * g4 + t;
-          bool vis = qvalid && kpos_s[key] <= qpos;
-          float v = s[b][t] * a.scale_log2;
-          if constexpr (FP8) v *= ksc_s[key];
-          v = vis ? v : -INFINITY;
-          s[b][t] = v;
-          mx = fmaxf(mx, v);
-        }
-      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-      const float m_new = fmaxf(m_run, mx);
-      const float alpha = (m_new == -INFINITY) ? 1.f : exp2f(m_run - m_new);
-      float psum = 0.f;
+          const float* vrow = Vs + (16 * b + 4 * g4 + t) * C::KLD;
 #pragma unroll
-      for (int b = 0; b < NB; b++)
+          for (int i = 0; i < ND; i++) o[i] = mfma_f32(vrow[16 * i + qi], s[b][t], o[i]);
+        }
+    } else {
+#pragma unroll
+      for (int b2 = 0; b2 < NB / 2; b2++) {
+        u16x8 pb;
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-          float pv = (s[b][t] == -INFINITY) ? 0.f : exp2f(s[b][t] - m_new);
-          s[b][t] = pv;
-          psum += pv;
+          float p0 = s[2 * b2][t], p1 = s[2 * b2 + 1][t];
+          if (FP8 && tile_fp8) {
+            p0 *= vsc_s[32 * b2 + 4 * g4 + t];
+            p1 *= vsc_s[32 * b2 + 16 + 4 * g4 + t];
+          }
+          pb[t] = f2bf(p0);
+          pb[4 + t] = f2bf(p1);
         }
-      l_run = l_run * alpha + psum;
-      m_run = m_new;
 #pragma unroll
-      for (int i = 0; i < ND; i++) o[i] *= alpha;
-
-      // ---- O^T[d][query] += V^T[d][key] P^T[key][query]
-      if constexpr (C::F32) {
-#pragma unroll
-        for (int b = 0; b < NB; b++)
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            const float* vrow = Vs + (16 * b + 4 * g4 + t) * C::KLD;
-#pragma unroll
-            for (int i = 0; i < ND; i++) o[i] = mfma_f32(vrow[16 * i + qi], s[b][t], o[i]);
-          }
-      } else {
-#pragma unroll
-        for (int b2 = 0; b2 < NB / 2; b2++) {
-          u16x8 pb;
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            float p0 = s[2 * b2][t], p1 = s[2 * b2 + 1][t];
-            if constexpr (FP8) {
-              p0 *= vsc_s[32 * b2 + 4 * g4 + t];
-              p1 *= vsc_s[32 * b2 + 16 + 4 * g4 + t];
-            }
-            pb[t] = f2bf(p0);
-            pb[4 + t] = f2bf(p1);
-          }
-#pragma unroll
-          for (int i = 0; i < ND; i++) {
-            const bf16_t* vt = Vs + (16 * i + qi) * C::VTLD + 32 * b2 + 4 * g4;
-            u32x2 lo = *reinterpret_cast<const u32x2*>(vt);
-            u32x2 hi = *reinterpret_cast<const u32x2*>(vt + 16);
-            u32x4 va = {lo[0], lo[1], hi[0], hi[1]};
-            o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), pb, o[i]);
-          }
+        for (int i = 0; i < ND; i++) {
+          const bf16_t* vt = Vs + (16 * i + qi) * C::VTLD + 32 * b2 + 4 * g4;
+          u32x2 lo = *reinterpret_cast<const u32x2*>(vt);
+          u32x2 hi = *reinterpret_cast<const u32x2*>(vt + 16);
+          u32x4 va = {lo[0], lo[1], hi[0], hi[1]};
+          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), pb, o[i]);
         }
       }
     }
@@ -335,14 +400,8 @@ __global__ __launch_bounds__(NW * 64) void attn_kernel(AttnArgs a) {
 
 template <typename TC, typename TKV, int D>
 static hipError_t launch_d(const AttnArgs& a, hipStream_t st) {
-  int rows = a.G * a.Pmax;
-  dim3 grid(a.n_work, a.Hkv);
-  if (rows <= 16)
-    hipLaunchKernelGGL((attn_kernel<TC, TKV, D, 1>), grid, dim3(64), 0, st, a);
-  else if (rows <= 32)
-    hipLaunchKernelGGL((attn_kernel<TC, TKV, D, 2>), grid, dim3(128), 0, st, a);
-  else
-    hipLaunchKernelGGL((attn_kernel<TC, TKV, D, 4>), grid, dim3(256), 0, st, a);
+  dim3 grid((unsigned)((int64_t)a.n_work * a.Hkv));
+  hipLaunchKernelGGL((attn_kernel<TC, TKV, D>), grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

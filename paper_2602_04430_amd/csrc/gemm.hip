@@ -185,9 +185,11 @@ static const TileCfg kBf16Tiles[] = {
     {256, 128, 64, 128, 64, "bf16_256x128x64_w128x64"},
     {128, 256, 64, 64, 128, "bf16_128x256x64_w64x128"},
     {64, 128, 64, 32, 64, "bf16_64x128x64_w32x64"},
+    {256, 256, 64, 128, 128, "bf16_256x256x64_w128x128"},
+    {256, 256, 32, 128, 128, "bf16_256x256x32_w128x128"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 3 : 4; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 3 : 6; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -230,7 +232,9 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 0: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64>(A, B, C, s, st);
       case 1: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64>(A, B, C, s, st);
       case 2: return launch_t<T, TO, EPI, 128, 256, 64, 64, 128>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64>(A, B, C, s, st);
+      case 3: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64>(A, B, C, s, st);
+      case 4: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 256, 256, 32, 128, 128>(A, B, C, s, st);
     }
   }
 }
