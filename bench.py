@@ -45,6 +45,10 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 path")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-cache variant")
     ap.add_argument("--cpu-sample", type=int, default=2, help="documents the oracle is timed on")
+    ap.add_argument("--proxy-train", type=int, default=16384,
+                    help="documents the proxy is trained on (labels from the full BF16 r=1 operator)")
+    ap.add_argument("--proxy-epochs", type=int, default=20)
+    ap.add_argument("--no-proxy", action="store_true")
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -111,6 +115,9 @@ def main():
     result = {}
     # ------------------------------------------------------------------ BF16 path
     mb = K.kvop_model_create(cfg, flat, K.KVOP_BF16)
+    proxy = None
+    if not args.no_proxy:
+        proxy, proxy_info = train_proxy(K, synth, mb, shape, wl.suffix, args, dev)
     probe = K.kvop_pool_create(mb, K.KVOP_KV_BF16, 1 << 20)
     need = sum(K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths)
     K.kvop_pool_destroy(probe)
@@ -136,6 +143,10 @@ def main():
     timed_eval(pool, 1.0, hb, steps=1)
     prof = K.kvop_profile_stop()
     log("profile (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in prof.items()})
+    cascade = None
+    if proxy is not None:
+        cascade = time_cascade(K, proxy, proxy_info, pool, hb, pooled, lists[1.0], op, bf16_out[1.0], n, args, dev,
+                               stream)
     K.kvop_pool_destroy(pool)
     # ------------------------------------------------------------------ FP8 cache
     if not args.no_fp8:
@@ -203,22 +214,33 @@ def main():
     att_bytes = (k1 + 32 * n) * 2 * shape.n_kv_heads * shape.head_dim * 2 * shape.n_layers
     roof_att = {"bound": "hbm", "achieved": att_bytes / (att_ms / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": att_bytes / (att_ms / 1e3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": att_ms / max(1, att_cnt)}
-    value = n / (headline_ms / 1e3)
+    plain_value = n / (headline_ms / 1e3)
+    value, step_ms, path = plain_value, headline_ms, "bf16 weights/activations, bf16 KV cache, no proxy"
+    if cascade is not None:
+        value, step_ms = cascade["tuples_per_s"], cascade["ms"]
+        path = (f"learned proxy (tau={cascade['tau']}) answers confident tuples, the full bf16 operator "
+                f"(bf16 KV cache, r=1) the rest")
     line = {
         "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": headline_ms, "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "plain semantic filter at scale: 16-layer d2048 GQA decoder, 4096 docs "
                                "lognormal(median 512, sigma 1) in [64,4096], 32-token suffix, r=1.0",
-                   "path": "bf16 weights/activations, bf16 KV cache (proxy stage not yet in the timed path)",
+                   "path": path,
                    "docs": n, "sum_L": k1},
         "roofline": roofline,
         "roofline_attention": roof_att,
         "kernel_ms_per_step": {k: round(v[0], 3) for k, v in prof.items()},
+        "bf16_plain_tuples_per_s": plain_value,
+        "proxy": cascade,
         "per_r": per_r,
         "kv_build_bf16_s": result["kv_build_bf16_s"],
         "cpu_baseline": cpu,
     }
+    if fp32 is not None and cascade is not None:
+        cascade["vs_fp32_plain_decision_disagreement"] = float(np.mean(cascade.pop("_final") != fp32["dec"]))
+    elif cascade is not None:
+        cascade.pop("_final")
     if fp32 is not None:
         d16 = bf16_out[1.0][1]
         lo32 = fp32["logits"][:, 0] - fp32["logits"][:, 1]
@@ -231,6 +253,132 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(json.dumps(line) + "\n")
+
+
+def train_proxy(K, synth, mb, shape, suffix, args, dev):
+    """Build training documents in waves (pooled features from kv_build, labels from the
+    full BF16 r=1 filter), then train the proxy with Adam and pick tau on a held-out split."""
+    import torch
+    t0 = time.time()
+    docs = synth.make_docs_lognormal(args.proxy_train, 512, 64, 4096, shape.vocab, seed=0, stream=101)
+    n = len(docs.lengths)
+    feats = torch.empty(n, shape.d_model, dtype=torch.float32, device=dev)
+    lo = np.empty(n, np.float64)
+    probe = K.kvop_pool_create(mb, K.KVOP_KV_BF16, 1 << 20)
+    sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
+    K.kvop_pool_destroy(probe)
+    cap = min(torch.cuda.mem_get_info()[0] - (40 << 30), sum(sizes) + (1 << 30))
+    pool = K.kvop_pool_create(mb, K.KVOP_KV_BF16, cap)
+    toks = torch.from_numpy(docs.tokens).to(dev)
+    op = K.make_op(K.KVOP_FILTER, suffix, synth.YES_ID, synth.NO_ID)
+    a = 0
+    while a < n:
+        b, acc = a, 0
+        while b < n and acc + sizes[b] <= cap - (1 << 28):
+            acc += sizes[b]
+            b += 1
+        offs = docs.offsets[a:b + 1] - docs.offsets[a]
+        h = K.kvop_kv_build(pool, toks[int(docs.offsets[a]):int(docs.offsets[b])], offs, feats[a:b])
+        idx, ioffs = synth.full_lists(docs.lengths[a:b])
+        lg = torch.empty(b - a, 2, dtype=torch.float32, device=dev)
+        K.kvop_op_eval(pool, op, 1.0, torch.from_numpy(idx).to(dev), ioffs, h, lg, None)
+        lgc = lg.cpu().numpy().astype(np.float64)
+        lo[a:b] = lgc[:, 0] - lgc[:, 1]
+        K.kvop_kv_release(pool, h)
+        log(f"proxy data [{a}, {b}) done at {time.time() - t0:.1f} s")
+        a = b
+    K.kvop_pool_destroy(pool)
+    del toks
+    labels_np = (lo > 0).astype(np.int32)
+    pos_frac = float(labels_np.mean())
+    log(f"proxy labels: {pos_frac:.3f} accepted")
+    n_tr = int(n * 0.8)
+    labels = torch.from_numpy(labels_np).to(dev)
+    p0 = synth.proxy_init(shape.d_model, 256, 2, 0)
+    packed = np.concatenate([p0["w1"].ravel(), p0["b1"], p0["w2"].ravel(), p0["b2"]]).astype(np.float32)
+    px = K.kvop_proxy_create(shape.d_model, 256, torch.from_numpy(packed).to(dev))
+    K.kvop_proxy_fit_standardizer(px, feats[:n_tr])
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    bs = 512
+    t1 = time.time()
+    for ep in range(args.proxy_epochs):
+        order = torch.from_numpy(synth.proxy_order(n_tr, ep, 0)).to(dev)
+        for s0 in range(0, n_tr - bs + 1, bs):
+            K.kvop_proxy_train_step(px, feats, labels, order[s0:s0 + bs], bs, 1e-3, loss)
+        log(f"proxy epoch {ep}: loss {float(loss.item()):.4f}")
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    # held-out split: disagreement with the full operator among all tuples, per tau
+    nh = n - n_tr
+    cls = torch.empty(nh, dtype=torch.int8, device=dev)
+    conf = torch.empty(nh, dtype=torch.float32, device=dev)
+    ans = torch.empty(nh, dtype=torch.int8, device=dev)
+    held = {}
+    tau_star = None
+    for tau in (0.9, 0.95, 0.99):
+        K.kvop_proxy_infer(px, feats[n_tr:], tau, cls, conf, ans)
+        c, an = cls.cpu().numpy(), ans.cpu().numpy().astype(bool)
+        dis = float(np.mean((c != labels_np[n_tr:]) & an))
+        held[str(tau)] = {"coverage": float(an.mean()), "disagreement": dis}
+        if tau_star is None and dis <= 0.01:
+            tau_star = tau
+    if tau_star is None:
+        tau_star = 0.99
+    log(f"proxy held-out: {held}, tau* = {tau_star}")
+    info = {"train_docs": n_tr, "heldout_docs": nh, "label_accept_frac": pos_frac, "train_s": t_train,
+            "data_s": time.time() - t0 - t_train, "heldout": held, "tau": tau_star}
+    return px, info
+
+
+def time_cascade(K, px, info, pool, handles, pooled, lists, op, full_out, n, args, dev, stream):
+    """Timed step: proxy inference on the documents' pooled features, then the full operator
+    on the tuples the proxy leaves unsure (a two-stage cascade)."""
+    import torch
+    idx, offs = lists
+    tau = info["tau"]
+    cls = torch.empty(n, dtype=torch.int8, device=dev)
+    conf = torch.empty(n, dtype=torch.float32, device=dev)
+    ans = torch.empty(n, dtype=torch.int8, device=dev)
+    lg = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    dec = torch.empty(n, dtype=torch.int8, device=dev)
+    final = None
+
+    def step():
+        K.kvop_proxy_infer(px, pooled, tau, cls, conf, ans)
+        a = ans.cpu().numpy().astype(bool)            # synchronises: the host routes the unsure tuples
+        sel = np.nonzero(~a)[0].astype(np.int32)
+        if len(sel):
+            K.kvop_op_eval_select(pool, op, 1.0, idx, offs, handles, sel, lg, dec)
+        return a, sel
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        a, sel = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = max(e0.elapsed_time(e1), (time.time() - t0) * 1e3) / args.steps
+    full_dec = full_out[1]
+    c = cls.cpu().numpy()
+    d = dec.cpu().numpy()
+    final = np.where(a, c, d)
+    per_tau = {}
+    for t in (0.9, 0.95, 0.99):
+        K.kvop_proxy_infer(px, pooled, t, cls, conf, ans)
+        cc, an = cls.cpu().numpy(), ans.cpu().numpy().astype(bool)
+        per_tau[str(t)] = {"coverage": float(an.mean()),
+                           "disagreement_vs_full_operator": float(np.mean((cc != full_dec) & an))}
+    out = {"tau": tau, "tuples_per_s": n / (ms / 1e3), "ms": ms, "coverage": float(a.mean()),
+           "sent_to_full_operator": int(len(sel)),
+           "disagreement_vs_full_operator": float(np.mean(final != full_dec)),
+           "per_tau_on_workload": per_tau, "training": info, "_final": final}
+    log(f"cascade: {out['tuples_per_s']:.0f} tuples/s, coverage {out['coverage']:.3f}, "
+        f"disagreement {out['disagreement_vs_full_operator']:.4f}")
+    return out
 
 
 def oracle_baseline(shape, w, docs, suffix, n_sample, gpu_bf16_logits, gpu_f32_logits):

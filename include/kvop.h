@@ -166,6 +166,48 @@ kvop_status kvop_op_eval(kvop_pool* pool, const kvop_op* op, float r, const int3
                          void* stream, float* logits_out_dev, int8_t* decision_out_dev,
                          int32_t* tokens_out_dev);
 
+/* Cascade entry: evaluate only the items listed in select_host (indices into the
+ * n_items items described by handles/lists, as for kvop_op_eval), writing their outputs
+ * at their own rows of logits_out_dev / decision_out_dev; other rows are untouched.
+ * Filters and joins only (a map is rejected with EINVAL).  Used to send the items a
+ * cheaper first stage left unsure to the full operator (Section 4.1, Eqs. 1-3). */
+kvop_status kvop_op_eval_select(kvop_pool* pool, const kvop_op* op, float r, const int32_t* idx_dev,
+                                const int64_t* idx_offsets_host, const kvop_handle* handles_host, int32_t n_items,
+                                const int32_t* select_host, int32_t n_select, void* stream, float* logits_out_dev,
+                                int8_t* decision_out_dev);
+
+/* ---- learned proxy ----------------------------------------------------------
+ * The cheap first stage of a two-stage cascade (Section 4.1, Eqs. 1-3: an operator
+ * accepts or rejects a tuple, or passes it on as unsure).  Network:
+ *   x = (f - mean) * inv_std        (feature standardiser, identity until fitted)
+ *   z = W2 gelu(W1 x + b1) + b2,  p = softmax(z);  class 1 = accept
+ * with exact (erf) GELU.  Parameters are FP32 masters packed as
+ *   W1 [d_hidden, d_in] | b1 [d_hidden] | W2 [2, d_hidden] | b2 [2];
+ * the forward projection and the W1 gradient run in BF16 on MFMA with FP32
+ * accumulation; everything else is FP32.  Training minimises the mean
+ * cross-entropy with bias-corrected Adam (beta 0.9 / 0.999, eps 1e-8). */
+kvop_status kvop_proxy_create(int32_t d_in, int32_t d_hidden, const float* params_dev, kvop_proxy** out);
+kvop_status kvop_proxy_destroy(kvop_proxy* proxy);
+/* mean and 1/std (std floored at 1e-6) of every feature over feats_dev [n, d_in] */
+kvop_status kvop_proxy_fit_standardizer(kvop_proxy* proxy, const float* feats_dev, int64_t n, void* stream);
+kvop_status kvop_proxy_set_standardizer(kvop_proxy* proxy, const float* mean_dev, const float* inv_std_dev,
+                                        void* stream);
+/* One Adam step on the minibatch rows_dev[0..batch) of feats_dev/labels_dev (labels in
+ * {0, 1}); rows_dev NULL means rows 0..batch-1.  batch must be a multiple of 8.
+ * loss_out_dev (nullable) receives the minibatch's mean cross-entropy before the step. */
+kvop_status kvop_proxy_train_step(kvop_proxy* proxy, const float* feats_dev, const int32_t* labels_dev,
+                                  const int32_t* rows_dev, int32_t batch, float lr, void* stream,
+                                  float* loss_out_dev);
+/* Gradients of the minibatch's mean cross-entropy, packed like the parameters (no update). */
+kvop_status kvop_proxy_grads(kvop_proxy* proxy, const float* feats_dev, const int32_t* labels_dev,
+                             const int32_t* rows_dev, int32_t batch, void* stream, float* grads_out_dev,
+                             float* loss_out_dev);
+/* Inference over n rows: class (0/1), confidence max(p), answered = confidence > tau. */
+kvop_status kvop_proxy_infer(kvop_proxy* proxy, const float* feats_dev, int64_t n, float tau, void* stream,
+                             int8_t* cls_out_dev, float* conf_out_dev, int8_t* answered_out_dev);
+/* Copy the FP32 master parameters (packed as above) into params_out_dev. */
+kvop_status kvop_proxy_params(kvop_proxy* proxy, float* params_out_dev, void* stream);
+
 /* ---- diagnostics and tuning ------------------------------------------------
  * Run one projection C = A B^T with an explicit tile configuration `tile`
  * (0 .. kvop_gemm_num_tiles(dtype)-1, or -1 for the library's own choice).  dtype: KVOP_F32 or KVOP_BF16 operands;

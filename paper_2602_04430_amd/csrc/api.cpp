@@ -14,30 +14,15 @@
 #include <vector>
 
 #include "../../include/kvop.h"
+#include "host_util.h"
 #include "kernels.h"
 
 using namespace kvop;
 
 namespace {
 
-thread_local std::string g_err;
-
-kvop_status fail(kvop_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
-}
-
-#define HIPTRY(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(KVOP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
-  } while (0)
-
 constexpr int kRopeMaxPos = 65536;
 constexpr int64_t kAlign = 256;
-
-int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // ---- optional per-kernel-class timing: HIP events recorded on the caller's stream around
 // each launch while profiling is on; read back (synchronising) by kvop_profile_stop.
@@ -69,33 +54,6 @@ struct ProfScope {
   ~ProfScope() {
     if (a) { (void)hipEventRecord(b, st); g_prof.pending.push_back({k, {a, b}}); }
   }
-};
-
-// Device buffer that grows on demand (synchronising the stream before a reallocation).
-struct DevBuf {
-  void* p = nullptr;
-  size_t cap = 0;
-  hipError_t reserve(size_t bytes, hipStream_t st) {
-    if (bytes <= cap) return hipSuccess;
-    if (p) {
-      hipError_t e = hipStreamSynchronize(st);
-      if (e != hipSuccess) return e;
-      (void)hipFree(p);
-      p = nullptr;
-      cap = 0;
-    }
-    size_t want = std::max(bytes, cap + cap / 2);
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      e = hipMalloc(&p, bytes);
-      if (e != hipSuccess) { p = nullptr; return e; }
-      want = bytes;
-    }
-    cap = want;
-    return hipSuccess;
-  }
-  ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
 // Pinned host staging with an event guarding its reuse.
@@ -390,7 +348,7 @@ LayerBufs carve(kvop_model* m, char* base, int64_t rows, bool join) {
 
 extern "C" {
 
-const char* kvop_last_error(void) { return g_err.c_str(); }
+const char* kvop_last_error(void) { return last_error().c_str(); }
 
 int64_t kvop_weights_numel(const kvop_model_cfg* c) {
   if (!c) return -1;
@@ -500,7 +458,7 @@ kvop_status kvop_model_create(const kvop_model_cfg* cfg, const float* w, int64_t
   }
   if (st_ok != KVOP_OK) {
     delete m;
-    return fail(KVOP_EDEVICE, g_err.empty() ? "model upload failed" : g_err);
+    return fail(KVOP_EDEVICE, last_error().empty() ? "model upload failed" : last_error());
   }
   *out = m;
   return KVOP_OK;
@@ -723,11 +681,11 @@ kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* of
 }
 
 // ------------------------------------------------------------------ op_eval
-kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
-                         const kvop_handle* hs, int32_t n_items, void* stream, float* logits, int8_t* decision,
-                         int32_t* tokens_out) {
-  if (!p || !op || n_items < 0) return fail(KVOP_EINVAL, "bad arguments");
-  if (n_items == 0) return KVOP_OK;
+static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
+                                const kvop_handle* hs, int32_t n_items, const int32_t* select, int32_t n_select,
+                                void* stream, float* logits, int8_t* decision, int32_t* tokens_out) {
+  if (!p || !op || n_items < 0 || n_select < 0) return fail(KVOP_EINVAL, "bad arguments");
+  if (n_items == 0 || (select && n_select == 0)) return KVOP_OK;
   kvop_model* m = p->m;
   const kvop_model_cfg& c = m->cfg;
   hipStream_t st = (hipStream_t)stream;
@@ -750,20 +708,32 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
   }
   const bool join = kind == KVOP_JOIN;
   const int per = join ? 2 : 1;
-  const int n_lists = n_items * per;
+  if (select && kind == KVOP_MAP) return fail(KVOP_EINVAL, "item selection applies to filters and joins");
+  // evaluated items (all, or the selection) and their lists: list lidx[i*per + j]
+  const int n_eval = select ? n_select : n_items;
+  std::vector<int32_t> ids(n_eval);
+  for (int i = 0; i < n_eval; i++) {
+    ids[i] = select ? select[i] : i;
+    if (ids[i] < 0 || ids[i] >= n_items) return fail(KVOP_EINVAL, "selected item out of range");
+  }
+  const int n_lists = n_eval * per;
+  std::vector<int64_t> lidx(n_lists);
+  for (int i = 0; i < n_eval; i++)
+    for (int j = 0; j < per; j++) lidx[i * per + j] = (int64_t)ids[i] * per + j;
   std::vector<const DocSlot*> docs(n_lists);
   std::vector<ListCheck> checks(n_lists);
   for (int i = 0; i < n_lists; i++) {
-    docs[i] = lookup(p, hs[i]);
-    if (!docs[i]) return fail(KVOP_EBADHANDLE, "handle " + std::to_string(i) + " is not live in this pool");
-    int64_t k = idx_off[i + 1] - idx_off[i];
-    if (k < 1 || k > docs[i]->L) return fail(KVOP_EINVAL, "list " + std::to_string(i) + " has a bad length");
+    const int64_t li = lidx[i];
+    docs[i] = lookup(p, hs[li]);
+    if (!docs[i]) return fail(KVOP_EBADHANDLE, "handle " + std::to_string(li) + " is not live in this pool");
+    int64_t k = idx_off[li + 1] - idx_off[li];
+    if (k < 1 || k > docs[i]->L) return fail(KVOP_EINVAL, "list " + std::to_string(li) + " has a bad length");
     if (!(op->flags & KVOP_FLAG_ANY_COUNT) && k != retained_count(r, docs[i]->L))
-      return fail(KVOP_EINVAL, "list " + std::to_string(i) + " holds " + std::to_string(k) + " rows, k(r, L) = " +
+      return fail(KVOP_EINVAL, "list " + std::to_string(li) + " holds " + std::to_string(k) + " rows, k(r, L) = " +
                                    std::to_string(retained_count(r, docs[i]->L)));
-    checks[i] = ListCheck{idx_off[i], (int32_t)k, docs[i]->L};
+    checks[i] = ListCheck{idx_off[li], (int32_t)k, docs[i]->L};
   }
-  for (int i = 0; i < n_items; i++) {
+  for (int i = 0; i < n_eval; i++) {
     int64_t top = join ? (int64_t)docs[2 * i]->L + docs[2 * i + 1]->L : docs[i]->L;
     if (top + S + n_gen >= kRopeMaxPos) return fail(KVOP_EINVAL, "positions exceed the rotary table");
   }
@@ -792,8 +762,8 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
   const int rows_per_item = S + (kind == KVOP_MAP ? n_gen - 1 : 0);  // own rows kept for decoding
   const int e = m->esz();
 
-  for (int w0 = 0; w0 < n_items; w0 += wave_items) {
-    const int B = std::min(wave_items, n_items - w0);
+  for (int w0 = 0; w0 < n_eval; w0 += wave_items) {
+    const int B = std::min(wave_items, n_eval - w0);
     const int64_t rows = (int64_t)B * S;
     // per-row positions and (joins) rotation shifts; per-item work items
     std::vector<int32_t> pos(rows), shift(join ? rows : 0);
@@ -811,15 +781,17 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
       }
       for (int q0 = 0; q0 < S; q0 += Pmax_s) {
         AttnWork w{};
+        const int64_t la = lidx[it * per];
         w.off_a = (int64_t)A->off;
-        w.idx_a = idx_off[it * per];
+        w.idx_a = idx_off[la];
         w.L_a = A->L;
-        w.n_a = (int32_t)(idx_off[it * per + 1] - idx_off[it * per]);
+        w.n_a = (int32_t)(idx_off[la + 1] - idx_off[la]);
         if (join) {
+          const int64_t lb = lidx[it * per + 1];
           w.off_b = (int64_t)Bd->off;
-          w.idx_b = idx_off[it * per + 1];
+          w.idx_b = idx_off[lb];
           w.L_b = Bd->L;
-          w.n_b = (int32_t)(idx_off[it * per + 2] - idx_off[it * per + 1]);
+          w.n_b = (int32_t)(idx_off[lb + 1] - idx_off[lb]);
         } else {
           w.off_b = -1;
           w.idx_b = -1;
@@ -846,10 +818,10 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
         AttnWork w{};
         w.off_a = (int64_t)A->off;
         w.off_b = -1;
-        w.idx_a = idx_off[it];
+        w.idx_a = idx_off[lidx[it]];
         w.idx_b = -1;
         w.L_a = A->L;
-        w.n_a = (int32_t)(idx_off[it + 1] - idx_off[it]);
+        w.n_a = (int32_t)(idx_off[lidx[it] + 1] - idx_off[lidx[it]]);
         w.q_row0 = b;
         w.n_q = 1;
         w.own_row0 = b * rows_per_item;
@@ -865,7 +837,9 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
         }
     }
     std::vector<int32_t> suffix(op->suffix_host, op->suffix_host + S);
+    std::vector<int32_t> out_rows(ids.begin() + w0, ids.begin() + w0 + B);
     Mirror mir;
+    size_t o_out = mir.add(out_rows.size() * 4);
     size_t o_pos = mir.add(pos.size() * 4), o_shift = mir.add(shift.size() * 4),
            o_work = mir.add(work.size() * sizeof(AttnWork)), o_suf = mir.add(S * 4),
            o_dwork = mir.add(dwork.size() * sizeof(AttnWork)), o_os = mir.add(own_src.size() * 4),
@@ -879,6 +853,7 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
     if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
       return fail(KVOP_ENOMEM, "metadata staging");
     char* hp = m->stage.p;
+    memcpy(hp + o_out, out_rows.data(), out_rows.size() * 4);
     memcpy(hp + o_pos, pos.data(), pos.size() * 4);
     if (join) memcpy(hp + o_shift, shift.data(), shift.size() * 4);
     memcpy(hp + o_work, work.data(), work.size() * sizeof(AttnWork));
@@ -943,16 +918,16 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
     if (kind != KVOP_MAP) {
       ProfScope ps(PC_HEAD, st);
       HIPTRY(head_filter(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->yes_id, op->no_id,
-                         op->theta_pos, op->theta_neg, logits + (int64_t)w0 * 2, decision ? decision + w0 : nullptr,
-                         st));
+                         op->theta_pos, op->theta_neg, (const int32_t*)(md + o_out), logits, decision, st));
       continue;
     }
     // ---- map: step 1 from the suffix's last row, then n_gen - 1 decode steps
     const int ln = op->label_n;
     int32_t* ntok = (int32_t*)(md + o_ntok);
-    float* lg = logits + (int64_t)w0 * n_gen * ln;
-    int32_t* tk = tokens_out + (int64_t)w0 * n_gen;
-    HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, lg,
+    float* lg = logits;
+    int32_t* tk = tokens_out;
+    const int32_t* orow = (const int32_t*)(md + o_out);
+    HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, orow, lg,
                     (int64_t)n_gen * ln, tk, n_gen, ntok, st));
     for (int t = 1; t < n_gen; t++) {
       // positions of the fed token: L + S + t - 1; it is own row S + t - 1 of its item
@@ -1034,11 +1009,26 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
           HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, s), bufs.act, W.wdown, bufs.x, s, st));
         }
       }
-      HIPTRY(head_map(m->dt, bufs.x, d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, lg + (int64_t)t * ln,
-                      (int64_t)n_gen * ln, tk + t, n_gen, ntok, st));
+      HIPTRY(head_map(m->dt, bufs.x, d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, orow,
+                      lg + (int64_t)t * ln, (int64_t)n_gen * ln, tk + t, n_gen, ntok, st));
     }
   }
   return KVOP_OK;
+}
+
+kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
+                         const kvop_handle* hs, int32_t n_items, void* stream, float* logits, int8_t* decision,
+                         int32_t* tokens_out) {
+  return op_eval_impl(p, op, r, idx, idx_off, hs, n_items, nullptr, 0, stream, logits, decision, tokens_out);
+}
+
+kvop_status kvop_op_eval_select(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx,
+                                const int64_t* idx_offsets, const kvop_handle* hs, int32_t n_items,
+                                const int32_t* select_host, int32_t n_select, void* stream, float* logits,
+                                int8_t* decision) {
+  if (!select_host && n_select > 0) return fail(KVOP_EINVAL, "null selection");
+  if (n_select == 0) return KVOP_OK;
+  return op_eval_impl(p, op, r, idx, idx_offsets, hs, n_items, select_host, n_select, stream, logits, decision, nullptr);
 }
 
 // ------------------------------------------------------------------ profiling

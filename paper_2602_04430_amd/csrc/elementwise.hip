@@ -281,8 +281,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void head_filter_kernel(const float* __restrict__ x, int64_t ldx, int d,
                                                           const float* __restrict__ g, float eps,
                                                           const T* __restrict__ W, int yes_id, int no_id, float thp,
-                                                          float thn, float* __restrict__ logits,
-                                                          int8_t* __restrict__ decision) {
+                                                          float thn, const int32_t* __restrict__ out_rows,
+                                                          float* __restrict__ logits, int8_t* __restrict__ decision) {
   __shared__ float red[3][4];
   int item = blockIdx.x;
   const float* xr = x + (int64_t)item * ldx;
@@ -309,23 +309,24 @@ __global__ __launch_bounds__(256) void head_filter_kernel(const float* __restric
   if (threadIdx.x == 0) {
     float ly = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     float ln = red[2][0] + red[2][1] + red[2][2] + red[2][3];
-    logits[2 * item] = ly;
-    logits[2 * item + 1] = ln;
+    const int64_t o = out_rows[item];
+    logits[2 * o] = ly;
+    logits[2 * o + 1] = ln;
     float lo = ly - ln;
-    if (decision) decision[item] = lo > thp ? 1 : (lo < thn ? 0 : -1);
+    if (decision) decision[o] = lo > thp ? 1 : (lo < thn ? 0 : -1);
   }
 }
 
 hipError_t head_filter(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, float* logits,
-                       int8_t* decision, hipStream_t st) {
+                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* out_rows,
+                       float* logits, int8_t* decision, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   if (dt == DT_F32)
     hipLaunchKernelGGL(head_filter_kernel<float>, dim3(n_items), dim3(256), 0, st, x, ldx, d, g, eps,
-                       (const float*)head, yes_id, no_id, th_pos, th_neg, logits, decision);
+                       (const float*)head, yes_id, no_id, th_pos, th_neg, out_rows, logits, decision);
   else
     hipLaunchKernelGGL(head_filter_kernel<bf16_t>, dim3(n_items), dim3(256), 0, st, x, ldx, d, g, eps,
-                       (const bf16_t*)head, yes_id, no_id, th_pos, th_neg, logits, decision);
+                       (const bf16_t*)head, yes_id, no_id, th_pos, th_neg, out_rows, logits, decision);
   return hipGetLastError();
 }
 
@@ -333,6 +334,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__ x, int64_t ldx, int d,
                                                        const float* __restrict__ g, float eps,
                                                        const T* __restrict__ W, int lo, int n,
+                                                       const int32_t* __restrict__ out_rows,
                                                        float* __restrict__ logits, int64_t ldl,
                                                        int32_t* __restrict__ tok_out, int64_t ldt,
                                                        int32_t* __restrict__ next_tok) {
@@ -362,9 +364,10 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
   // argmax, lowest index on ties
   float best = -INFINITY;
   int bi = 0x7fffffff;
+  const int64_t orow = out_rows[item];
   for (int j = threadIdx.x; j < n; j += 256) {
     float v = zl[j];
-    logits[(int64_t)item * ldl + j] = v;
+    logits[orow * ldl + j] = v;
     if (v > best || (v == best && j < bi)) { best = v; bi = j; }
   }
 #pragma unroll
@@ -380,22 +383,22 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
     int i = redi[0];
     for (int k = 1; k < 4; k++)
       if (red[k] > b || (red[k] == b && redi[k] < i)) { b = red[k]; i = redi[k]; }
-    tok_out[(int64_t)item * ldt] = lo + i;
+    tok_out[orow * ldt] = lo + i;
     if (next_tok) next_tok[item] = lo + i;
   }
 }
 
 hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                    const void* head, int lo, int n, float* logits, int64_t ld_logits, int32_t* tok_out,
-                    int64_t ld_tok, int32_t* next_tok, hipStream_t st) {
+                    const void* head, int lo, int n, const int32_t* out_rows, float* logits, int64_t ld_logits,
+                    int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   size_t lds = (size_t)(d + n) * sizeof(float);
   if (dt == DT_F32)
     hipLaunchKernelGGL(head_map_kernel<float>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps, (const float*)head,
-                       lo, n, logits, ld_logits, tok_out, ld_tok, next_tok);
+                       lo, n, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
   else
     hipLaunchKernelGGL(head_map_kernel<bf16_t>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps,
-                       (const bf16_t*)head, lo, n, logits, ld_logits, tok_out, ld_tok, next_tok);
+                       (const bf16_t*)head, lo, n, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
   return hipGetLastError();
 }
 

@@ -99,13 +99,14 @@ hipError_t copy_kv_rows(int dt, const void* qkv, int64_t ld, int kcol, int n_col
 hipError_t pooled_mean(const float* x, int d, const int64_t* row_off, int n_docs, int n_rows, const float* g,
                        float eps, float* inv_scratch, float* pooled, hipStream_t st);
 // filter/join head: y = rmsnorm(x[row_of_item]) * g; logits (yes, no); log-odds decision
+// item i of the launch writes output row out_rows[i]
 hipError_t head_filter(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, float* logits,
-                       int8_t* decision, hipStream_t st);
+                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* out_rows,
+                       float* logits, int8_t* decision, hipStream_t st);
 // map head: logits over [lo, lo+n) and argmax (lowest id on ties)
 hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                    const void* head, int lo, int n, float* logits, int64_t ld_logits, int32_t* tok_out,
-                    int64_t ld_tok, int32_t* next_tok, hipStream_t st);
+                    const void* head, int lo, int n, const int32_t* out_rows, float* logits, int64_t ld_logits,
+                    int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st);
 // index-list validation: counts lists that are unsorted or out of range into *bad
 struct ListCheck {
   int64_t off;
@@ -120,5 +121,20 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 // decode L rows of one cached (layer, head, K or V) block to FP32
 hipError_t read_cache(int kvdt, const uint8_t* region, int L, int D, int layer, int n_layers, int Hkv, int h, int kv,
                       float* out, hipStream_t st);
+
+// ---------------------------------------------------------------- learned proxy
+hipError_t proxy_stats(const float* F, int64_t n, int d, float* mean, float* istd, hipStream_t st);
+hipError_t proxy_gather(const float* F, int d, const int32_t* rows, int B, const float* mean, const float* istd,
+                        uint16_t* x, uint16_t* xT, hipStream_t st);
+hipError_t proxy_head_infer(const float* h1, int n, int H, const float* b1, const float* W2, const float* b2,
+                            float tau, int8_t* cls, float* conf, int8_t* answered, hipStream_t st);
+hipError_t proxy_head_train(const float* h1, int B, int H, const float* b1, const float* W2, const float* b2,
+                            const int32_t* labels, const int32_t* rows, float* a, float* dz, float* dh1, uint16_t* dh1T,
+                            float* loss_row, hipStream_t st);
+hipError_t proxy_reduce(const float* a, const float* dz, const float* dh1, const float* loss_row, int B, int H,
+                        float* g_b1, float* g_w2, float* g_b2, float* loss, hipStream_t st);
+hipError_t proxy_adam(float* p, const float* g, float* m, float* v, int64_t n, int64_t n_w1, uint16_t* w1b, float lr,
+                      float beta1, float beta2, float eps, int step, hipStream_t st);
+hipError_t f32_to_bf16(const float* s, uint16_t* d, int64_t n, hipStream_t st);
 
 }  // namespace kvop

@@ -62,6 +62,16 @@ _SIGS = {
                                   C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P]),
     "kvop_gemm_set_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "kvop_debug_read_cache": (C.c_int, [_P, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "kvop_op_eval_select": (C.c_int, [_P, C.POINTER(kvop_op), C.c_float, _P, _P, _P, C.c_int32, _P, C.c_int32, _P,
+                                      _P, _P]),
+    "kvop_proxy_create": (C.c_int, [C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
+    "kvop_proxy_destroy": (C.c_int, [_P]),
+    "kvop_proxy_fit_standardizer": (C.c_int, [_P, _P, C.c_int64, _P]),
+    "kvop_proxy_set_standardizer": (C.c_int, [_P, _P, _P, _P]),
+    "kvop_proxy_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
+    "kvop_proxy_grads": (C.c_int, [_P, _P, _P, _P, C.c_int32, _P, _P, _P]),
+    "kvop_proxy_infer": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
+    "kvop_proxy_params": (C.c_int, [_P, _P, _P]),
     "kvop_profile_start": (C.c_int, []),
     "kvop_profile_stop": (C.c_int, [_P, _P, C.c_int32]),
     "kvop_profile_num_classes": (C.c_int32, []),
@@ -223,3 +233,52 @@ def kvop_profile_num_classes() -> int:
 
 def kvop_profile_class_name(i: int) -> str:
     return lib().kvop_profile_class_name(i).decode()
+
+
+def kvop_op_eval_select(pool, op: kvop_op, r: float, idx_dev, idx_offsets, handles, select, logits_dev,
+                        decision_dev=None, stream=None) -> None:
+    offs, po = _host(idx_offsets, np.int64)
+    h, hp = _host(handles, np.uint64)
+    sel, sp = _host(select, np.int32)
+    n_items = len(h) // (2 if op.kind == KVOP_JOIN else 1)
+    _check(lib().kvop_op_eval_select(pool, C.byref(op), float(r), _dptr(idx_dev), po, hp, n_items, sp, len(sel),
+                                     _stream(stream), _dptr(logits_dev), _dptr(decision_dev)))
+
+
+def kvop_proxy_create(d_in: int, d_hidden: int, params_dev) -> C.c_void_p:
+    out = C.c_void_p()
+    _check(lib().kvop_proxy_create(d_in, d_hidden, _dptr(params_dev), C.byref(out)))
+    return out
+
+
+def kvop_proxy_destroy(proxy) -> None:
+    _check(lib().kvop_proxy_destroy(proxy))
+
+
+def kvop_proxy_fit_standardizer(proxy, feats_dev, stream=None) -> None:
+    _check(lib().kvop_proxy_fit_standardizer(proxy, _dptr(feats_dev), int(feats_dev.shape[0]), _stream(stream)))
+
+
+def kvop_proxy_set_standardizer(proxy, mean_dev, inv_std_dev, stream=None) -> None:
+    _check(lib().kvop_proxy_set_standardizer(proxy, _dptr(mean_dev), _dptr(inv_std_dev), _stream(stream)))
+
+
+def kvop_proxy_train_step(proxy, feats_dev, labels_dev, rows_dev, batch: int, lr: float, loss_dev=None,
+                          stream=None) -> None:
+    _check(lib().kvop_proxy_train_step(proxy, _dptr(feats_dev), _dptr(labels_dev), _dptr(rows_dev), batch, lr,
+                                       _stream(stream), _dptr(loss_dev)))
+
+
+def kvop_proxy_grads(proxy, feats_dev, labels_dev, rows_dev, batch: int, grads_dev, loss_dev=None,
+                     stream=None) -> None:
+    _check(lib().kvop_proxy_grads(proxy, _dptr(feats_dev), _dptr(labels_dev), _dptr(rows_dev), batch,
+                                  _stream(stream), _dptr(grads_dev), _dptr(loss_dev)))
+
+
+def kvop_proxy_infer(proxy, feats_dev, tau: float, cls_dev, conf_dev, answered_dev, stream=None) -> None:
+    _check(lib().kvop_proxy_infer(proxy, _dptr(feats_dev), int(feats_dev.shape[0]), tau, _stream(stream),
+                                  _dptr(cls_dev), _dptr(conf_dev), _dptr(answered_dev)))
+
+
+def kvop_proxy_params(proxy, out_dev, stream=None) -> None:
+    _check(lib().kvop_proxy_params(proxy, _dptr(out_dev), _stream(stream)))

@@ -1,0 +1,163 @@
+"""GPU parity of the learned proxy (forward, gradients, Adam) against the FP64 oracle, a
+learning test, and the cascade's subset evaluation."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import codecs
+from oracle import proxy as op
+from paper_2602_04430_amd import kvop as K
+from paper_2602_04430_amd import synth
+from tests.gpu_common import Engine, say
+
+pytestmark = pytest.mark.gpu
+
+D_IN, H = 256, 128
+
+
+def _pack(p):
+    return np.concatenate([p["w1"].ravel(), p["b1"], p["w2"].ravel(), p["b2"]]).astype(np.float32)
+
+
+def _unpack(v, d=D_IN, h=H):
+    v = np.asarray(v, np.float64)
+    o = h * d
+    return {"w1": v[:o].reshape(h, d), "b1": v[o:o + h], "w2": v[o + h:o + 3 * h].reshape(2, h), "b2": v[o + 3 * h:]}
+
+
+def _setup(seed=0, n=64):
+    rng = np.random.default_rng(seed)
+    feats = (rng.standard_normal((n, D_IN)) * 0.7 + rng.standard_normal(D_IN) * 0.3).astype(np.float32)
+    labels = rng.integers(0, 2, n).astype(np.int32)
+    p0 = synth.proxy_init(D_IN, H, 2, seed)
+    p0["b1"] = (rng.standard_normal(H) * 0.05).astype(np.float32)
+    p0["w2"] = (rng.standard_normal((2, H)) * 0.2).astype(np.float32)
+    mean = feats.mean(axis=0).astype(np.float32)
+    istd = (1.0 / np.maximum(feats.std(axis=0), 1e-6)).astype(np.float32)
+    px = K.kvop_proxy_create(D_IN, H, torch.from_numpy(_pack(p0)).cuda())
+    K.kvop_proxy_set_standardizer(px, torch.from_numpy(mean).cuda(), torch.from_numpy(istd).cuda())
+    return feats, labels, p0, mean, istd, px
+
+
+def _std_bf16(feats, mean, istd):
+    return codecs.bf16_round(((feats - mean) * istd).astype(np.float32)).astype(np.float64)
+
+
+def test_proxy_gradients_match_oracle(device):
+    feats, labels, p0, mean, istd, px = _setup(1, 64)
+    g = torch.empty(H * D_IN + 3 * H + 2, device=device)
+    loss = torch.empty(1, device=device)
+    rows = torch.arange(64, dtype=torch.int32, device=device).flip(0)      # a permuted minibatch
+    K.kvop_proxy_grads(px, torch.from_numpy(feats).cuda(), torch.from_numpy(labels).cuda(), rows, 64, g, loss)
+    torch.cuda.synchronize()
+    got = _unpack(g.cpu().numpy())
+    order = np.arange(64)[::-1]
+    # reference on the operands the BF16 path actually multiplies (rounded x and W1)
+    pr = {k: np.asarray(v, np.float64) for k, v in p0.items()}
+    pr["w1"] = codecs.bf16_round(p0["w1"]).astype(np.float64)
+    x = _std_bf16(feats, mean, istd)[order]
+    l_ref, g_ref = op.loss_and_grads(pr, x, labels[order])
+    assert abs(float(loss.item()) - l_ref) < 1e-5
+    for k, tol in (("w1", 1e-2), ("b1", 1e-4), ("w2", 1e-4), ("b2", 1e-5)):
+        err = np.max(np.abs(got[k] - g_ref[k])) / max(1e-12, np.max(np.abs(g_ref[k])))
+        say("grad", k, err)
+        assert err <= tol, (k, err)
+    # against the plain FP64 oracle (unrounded operands) the BF16 error stays at the BF16 level
+    l64, g64 = op.loss_and_grads({k: np.asarray(v, np.float64) for k, v in p0.items()},
+                                 ((feats - mean) * istd).astype(np.float64)[order], labels[order])
+    for k in g64:
+        assert np.max(np.abs(got[k] - g64[k])) / np.max(np.abs(g64[k])) <= 3e-2
+    K.kvop_proxy_destroy(px)
+
+
+def test_proxy_adam_step_matches_closed_form(device):
+    feats, labels, p0, mean, istd, px = _setup(2, 64)
+    g = torch.empty(H * D_IN + 3 * H + 2, device=device)
+    F, Y = torch.from_numpy(feats).cuda(), torch.from_numpy(labels).cuda()
+    K.kvop_proxy_grads(px, F, Y, None, 64, g)
+    K.kvop_proxy_train_step(px, F, Y, None, 64, 1e-3)
+    out = torch.empty_like(g)
+    K.kvop_proxy_params(px, out)
+    torch.cuda.synchronize()
+    grads = g.cpu().numpy().astype(np.float64)
+    p = _pack(p0).astype(np.float64)
+    ref, _, _ = op.adam_step(p, grads, np.zeros_like(p), np.zeros_like(p), 1, 1e-3)
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=0, atol=2e-6)
+    K.kvop_proxy_destroy(px)
+
+
+def test_proxy_inference_matches_oracle(device):
+    feats, labels, p0, mean, istd, px = _setup(3, 300)
+    n = len(feats)
+    cls = torch.empty(n, dtype=torch.int8, device=device)
+    conf = torch.empty(n, device=device)
+    ans = torch.empty(n, dtype=torch.int8, device=device)
+    K.kvop_proxy_infer(px, torch.from_numpy(feats).cuda(), 0.6, cls, conf, ans)
+    torch.cuda.synchronize()
+    pr = {k: np.asarray(v, np.float64) for k, v in p0.items()}
+    pr["w1"] = codecs.bf16_round(p0["w1"]).astype(np.float64)
+    _, _, _, probs = op.forward(pr, _std_bf16(feats, mean, istd))
+    ref_conf = probs.max(axis=1)
+    np.testing.assert_allclose(conf.cpu().numpy(), ref_conf, rtol=0, atol=1e-5)
+    c = cls.cpu().numpy()
+    clear = np.abs(probs[:, 1] - probs[:, 0]) > 1e-4
+    np.testing.assert_array_equal(c[clear], np.argmax(probs, axis=1)[clear])
+    a = ans.cpu().numpy()
+    clear = np.abs(ref_conf - 0.6) > 1e-4
+    np.testing.assert_array_equal(a[clear], (ref_conf > 0.6)[clear].astype(np.int8))
+    K.kvop_proxy_destroy(px)
+
+
+def test_proxy_learns_a_separable_rule(device):
+    rng = np.random.default_rng(4)
+    n = 4096
+    w_true = np.zeros(D_IN)
+    w_true[:16] = rng.standard_normal(16)
+    feats = rng.standard_normal((n, D_IN)).astype(np.float32)
+    labels = ((feats @ w_true) > 0).astype(np.int32)
+    p0 = synth.proxy_init(D_IN, H, 2, 4)
+    px = K.kvop_proxy_create(D_IN, H, torch.from_numpy(_pack(p0)).cuda())
+    F, Y = torch.from_numpy(feats).cuda(), torch.from_numpy(labels).cuda()
+    K.kvop_proxy_fit_standardizer(px, F[:3072])
+    loss = torch.empty(1, device=device)
+    losses = []
+    for epoch in range(8):
+        order = torch.from_numpy(synth.proxy_order(3072, epoch, 4)).cuda()
+        for b0 in range(0, 3072, 256):
+            K.kvop_proxy_train_step(px, F, Y, order[b0:b0 + 256], 256, 3e-3, loss)
+            losses.append(float(loss.item()))
+    say("proxy loss", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    cls = torch.empty(1024, dtype=torch.int8, device=device)
+    conf = torch.empty(1024, device=device)
+    ans = torch.empty(1024, dtype=torch.int8, device=device)
+    K.kvop_proxy_infer(px, F[3072:], 0.9, cls, conf, ans)
+    torch.cuda.synchronize()
+    a = ans.cpu().numpy().astype(bool)
+    acc = np.mean(cls.cpu().numpy()[a] == labels[3072:][a])
+    say("held-out coverage", a.mean(), "accuracy on answered", acc)
+    assert a.mean() > 0.3 and acc > 0.95
+    K.kvop_proxy_destroy(px)
+
+
+def test_op_eval_select_writes_only_selected_rows(device):
+    shape = synth.ModelShape(n_layers=2, d_model=256, n_heads=4, n_kv_heads=2, head_dim=64, d_ffn=512, vocab=512)
+    w = synth.make_weights(shape, 11)
+    docs = synth.make_docs_uniform(30, 1, 90, shape.vocab, seed=11)
+    suffix = synth.suffix_tokens(8, shape.vocab, seed=11)
+    eng = Engine(shape, w, "bf16", "bf16")
+    handles = eng.build(docs)
+    idx, offs = synth.retained_lists(docs.lengths, 1.0, seed=11)
+    full_lg, full_dec = eng.filter(handles, idx, offs, suffix)
+    sel = np.array([3, 17, 0, 29, 8], np.int32)
+    opd = K.make_op(K.KVOP_FILTER, suffix, synth.YES_ID, synth.NO_ID)
+    lg = torch.full((30, 2), -7.0, device=device)
+    dec = torch.full((30,), 5, dtype=torch.int8, device=device)
+    K.kvop_op_eval_select(eng.pool, opd, 1.0, torch.from_numpy(idx).cuda(), offs, handles, sel, lg, dec)
+    torch.cuda.synchronize()
+    lg, dec = lg.cpu().numpy(), dec.cpu().numpy()
+    np.testing.assert_array_equal(lg[sel], full_lg[sel].astype(np.float32))
+    np.testing.assert_array_equal(dec[sel], full_dec[sel])
+    rest = np.setdiff1d(np.arange(30), sel)
+    assert np.all(lg[rest] == -7.0) and np.all(dec[rest] == 5)
+    eng.close()
