@@ -300,19 +300,36 @@ def train_proxy(K, synth, mb, shape, suffix, args, dev):
     K.kvop_proxy_fit_standardizer(px, feats[:n_tr])
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     bs = 512
+    nh = n - n_tr
+    cls = torch.empty(nh, dtype=torch.int8, device=dev)
+    conf = torch.empty(nh, dtype=torch.float32, device=dev)
+    ans = torch.empty(nh, dtype=torch.int8, device=dev)
+    best = torch.empty(shape.d_model * 256 + 3 * 256 + 2, dtype=torch.float32, device=dev)
+    best_loss, best_ep = float("inf"), -1
+
+    def val_loss():
+        K.kvop_proxy_infer(px, feats[n_tr:], 0.5, cls, conf, ans)
+        c, cf = cls.cpu().numpy(), conf.cpu().numpy().astype(np.float64)
+        p_true = np.where(c == labels_np[n_tr:], cf, 1.0 - cf)
+        return float(-np.mean(np.log(np.maximum(p_true, 1e-12))))
+
     t1 = time.time()
     for ep in range(args.proxy_epochs):
         order = torch.from_numpy(synth.proxy_order(n_tr, ep, 0)).to(dev)
         for s0 in range(0, n_tr - bs + 1, bs):
             K.kvop_proxy_train_step(px, feats, labels, order[s0:s0 + bs], bs, 1e-3, loss)
-        log(f"proxy epoch {ep}: loss {float(loss.item()):.4f}")
+        vl = val_loss()
+        if vl < best_loss:
+            best_loss, best_ep = vl, ep
+            K.kvop_proxy_params(px, best)
+        log(f"proxy epoch {ep}: train loss {float(loss.item()):.4f}, validation loss {vl:.4f}")
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    # held-out split: disagreement with the full operator among all tuples, per tau
-    nh = n - n_tr
-    cls = torch.empty(nh, dtype=torch.int8, device=dev)
-    conf = torch.empty(nh, dtype=torch.float32, device=dev)
-    ans = torch.empty(nh, dtype=torch.int8, device=dev)
+    # early stopping: keep the parameters of the best validation epoch
+    K.kvop_proxy_destroy(px)
+    px = K.kvop_proxy_create(shape.d_model, 256, best)
+    K.kvop_proxy_fit_standardizer(px, feats[:n_tr])
+    # validation split: disagreement with the full operator among all tuples, per tau
     held = {}
     tau_star = None
     for tau in (0.9, 0.95, 0.99):
@@ -324,9 +341,10 @@ def train_proxy(K, synth, mb, shape, suffix, args, dev):
             tau_star = tau
     if tau_star is None:
         tau_star = 0.99
-    log(f"proxy held-out: {held}, tau* = {tau_star}")
-    info = {"train_docs": n_tr, "heldout_docs": nh, "label_accept_frac": pos_frac, "train_s": t_train,
-            "data_s": time.time() - t0 - t_train, "heldout": held, "tau": tau_star}
+    log(f"proxy validation: {held}, best epoch {best_ep}, tau* = {tau_star}")
+    info = {"train_docs": n_tr, "validation_docs": nh, "label_accept_frac": pos_frac, "train_s": t_train,
+            "best_epoch": best_ep, "validation_loss": best_loss,
+            "data_s": time.time() - t0 - t_train, "validation": held, "tau": tau_star}
     return px, info
 
 

@@ -147,26 +147,27 @@ struct TileStage {
       }
     }
     if constexpr (!C::F32) {
+      // transposed V: element (d, key) at dword d * VTLD/2 + (key/2 ^ swz(d)), swz(d) = 2*((d/16)&7),
+      // so the 16 lanes of one store (16 different d blocks) hit 16 different banks
       uint32_t* vt = reinterpret_cast<uint32_t*>(Vs);
 #pragma unroll
       for (int i = 0; i < NVU; i++) {
         int u = tid + i * NT;
         int jp = u / CPR, cc = u % CPR;
         if (u >= (KT / 2) * CPR) continue;
-        int j0 = 2 * jp;
         if (!fp8) {
 #pragma unroll
           for (int e = 0; e < 8; e++) {
-            uint32_t a = (vr0[i][e >> 1] >> ((e & 1) * 16)) & 0xffff;
-            uint32_t b = (vr1[i][e >> 1] >> ((e & 1) * 16)) & 0xffff;
-            vt[((cc * 8 + e) * C::VTLD + j0) >> 1] = a | (b << 16);
+            const int d = cc * 8 + e;
+            vt[d * (C::VTLD / 2) + (jp ^ (2 * ((d >> 4) & 7)))] = pair_halves(vr0[i][e >> 1], vr1[i][e >> 1], e & 1);
           }
         } else if (cc < CPR / 2) {
 #pragma unroll
           for (int e = 0; e < 16; e++) {
+            const int d = cc * 16 + e;
             uint32_t a = e4m3_to_bf16((vr0[i][e >> 2] >> ((e & 3) * 8)) & 0xff);
             uint32_t b = e4m3_to_bf16((vr1[i][e >> 2] >> ((e & 3) * 8)) & 0xff);
-            vt[((cc * 16 + e) * C::VTLD + j0) >> 1] = a | (b << 16);
+            vt[d * (C::VTLD / 2) + (jp ^ (2 * ((d >> 4) & 7)))] = a | (b << 16);
           }
         }
       }
@@ -310,30 +311,34 @@ __global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
         }
       }
     }
-    // ---- mask, scale, online softmax (statistics in FP32)
+    // ---- online softmax in FP32.  Statistics are kept on raw scores (the scale is > 0) and
+    // the scale is folded into the exponent: p = 2^(s*c - m*c).  Only tiles that can hold an
+    // invisible key (a partial tile, own rows, causal prefill) are masked.
+    const bool need_mask = (ti >= TA + TB) || (ti < TA ? (ti + 1) * KT > src[0].n : (ti - TA + 1) * KT > src[1].n) ||
+                           kpos_s[KT - 1] > w.q_pos0;
     float mx = -INFINITY;
 #pragma unroll
     for (int b = 0; b < NB; b++)
 #pragma unroll
       for (int t = 0; t < 4; t++) {
-        int key = 16 * b + 4 * g4 + t;
-        bool vis = qvalid && kpos_s[key] <= qpos;
-        float v = s[b][t] * a.scale_log2;
-        if (FP8 && tile_fp8) v *= ksc_s[key];
-        v = vis ? v : -INFINITY;
+        float v = s[b][t];
+        if (FP8 && tile_fp8) v *= ksc_s[16 * b + 4 * g4 + t];
+        if (need_mask && !(kpos_s[16 * b + 4 * g4 + t] <= qpos)) v = -INFINITY;
         s[b][t] = v;
         mx = fmaxf(mx, v);
       }
     mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    const float c = a.scale_log2;
     const float m_new = fmaxf(m_run, mx);
-    const float alpha = (m_new == -INFINITY) ? 1.f : exp2f(m_run - m_new);
+    const float mc = m_new == -INFINITY ? 0.f : m_new * c;
+    const float alpha = __builtin_amdgcn_exp2f(m_run * c - mc);   // 0 when m_run = -inf
     float psum = 0.f;
 #pragma unroll
     for (int b = 0; b < NB; b++)
 #pragma unroll
       for (int t = 0; t < 4; t++) {
-        float pv = (s[b][t] == -INFINITY) ? 0.f : exp2f(s[b][t] - m_new);
+        float pv = __builtin_amdgcn_exp2f(fmaf(s[b][t], c, -mc));  // exp2(-inf) = 0
         s[b][t] = pv;
         psum += pv;
       }
@@ -355,24 +360,29 @@ __global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
     } else {
 #pragma unroll
       for (int b2 = 0; b2 < NB / 2; b2++) {
-        u16x8 pb;
+        u32x4 pb;
 #pragma unroll
-        for (int t = 0; t < 4; t++) {
-          float p0 = s[2 * b2][t], p1 = s[2 * b2 + 1][t];
+        for (int t = 0; t < 4; t += 2) {
+          float p0 = s[2 * b2][t], p0n = s[2 * b2][t + 1];
+          float p1 = s[2 * b2 + 1][t], p1n = s[2 * b2 + 1][t + 1];
           if (FP8 && tile_fp8) {
             p0 *= vsc_s[32 * b2 + 4 * g4 + t];
+            p0n *= vsc_s[32 * b2 + 4 * g4 + t + 1];
             p1 *= vsc_s[32 * b2 + 16 + 4 * g4 + t];
+            p1n *= vsc_s[32 * b2 + 16 + 4 * g4 + t + 1];
           }
-          pb[t] = f2bf(p0);
-          pb[4 + t] = f2bf(p1);
+          pb[t / 2] = pack_bf16x2(p0, p0n);
+          pb[2 + t / 2] = pack_bf16x2(p1, p1n);
         }
+        const int jp_lo = 16 * b2 + 2 * g4;
 #pragma unroll
         for (int i = 0; i < ND; i++) {
-          const bf16_t* vt = Vs + (16 * i + qi) * C::VTLD + 32 * b2 + 4 * g4;
-          u32x2 lo = *reinterpret_cast<const u32x2*>(vt);
-          u32x2 hi = *reinterpret_cast<const u32x2*>(vt + 16);
+          const bf16_t* vrow = Vs + (16 * i + qi) * C::VTLD;
+          const int sw = 2 * (i & 7);
+          u32x2 lo = *reinterpret_cast<const u32x2*>(vrow + 2 * (jp_lo ^ sw));
+          u32x2 hi = *reinterpret_cast<const u32x2*>(vrow + 2 * ((jp_lo + 8) ^ sw));
           u32x4 va = {lo[0], lo[1], hi[0], hi[1]};
-          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), pb, o[i]);
+          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
         }
       }
     }

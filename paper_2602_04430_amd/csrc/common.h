@@ -17,12 +17,27 @@ typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// float -> bfloat16, round to nearest even (NaN kept quiet)
+// float -> bfloat16, round to nearest even (NaN kept quiet).  On the device this is the
+// hardware conversion (v_cvt_pk_bf16_f32); the host keeps the same rounding in integer code.
 __device__ __host__ inline bf16_t f2bf(float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_bit_cast(bf16_t, (__bf16)f);
+#else
   uint32_t u = __builtin_bit_cast(uint32_t, f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (bf16_t)(u >> 16);
+#endif
+}
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// two floats -> packed bfloat16 pair (low = a), one v_cvt_pk_bf16_f32
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+  bf16x2_t v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
+}
+// low 16 bits from lo's half h, high 16 bits from hi's half h (one v_perm_b32)
+__device__ inline uint32_t pair_halves(uint32_t lo, uint32_t hi, int h) {
+  return __builtin_amdgcn_perm(hi, lo, h ? 0x07060302u : 0x05040100u);
 }
 __device__ __host__ inline float bf2f(bf16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 

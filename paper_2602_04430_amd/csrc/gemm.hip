@@ -18,18 +18,27 @@
 
 namespace kvop {
 
-template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI>
+// SWZ selects the LDS layout of a K-slab row (CPR 16-byte chunks):
+//   0: padded rows (BK + one chunk) — chunk c of row r at r*LDK + c*VEC
+//   1: unpadded, chunk c of row r stored at slot c ^ ((r >> 1) & (CPR-1))
+//   2: unpadded, chunk c of row r stored at slot c ^ (r & (CPR-1))
+template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
                                                       int64_t ldb, int64_t ldc, int tiles_m) {
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
-  constexpr int LDK = BK + VEC;             // padded LDS row (elements)
+  constexpr int LDK = BK + (SWZ == 0 ? VEC : 0);  // LDS row pitch (elements)
   constexpr int CPR = BK / VEC;             // chunks per tile row
   constexpr int ACH = BM * CPR / 256;
   constexpr int BCH = BN * CPR / 256;
   constexpr int MI = WM / 16, NI = WN / 16;
   constexpr int WN_CNT = BN / WN;
   constexpr int KSUB = 4 * VEC;             // K consumed per MFMA step group
+  auto slot = [](int r, int c) {            // LDS chunk slot of logical chunk c in row r
+    if constexpr (SWZ == 1) return c ^ ((r >> 1) & (CPR - 1));
+    else if constexpr (SWZ == 2) return c ^ (r & (CPR - 1));
+    else return c;
+  };
   static_assert((BM / WM) * (BN / WN) == 4, "4 wavefronts");
   static_assert(ACH * 256 == BM * CPR && BCH * 256 == BN * CPR, "tile/thread mismatch");
   static_assert(EPI != EPI_SWIGLU || (NI % 2 == 0), "swiglu needs gate/up block pairs");
@@ -75,13 +84,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
     T* Bs = As + BM * LDK;
 #pragma unroll
     for (int i = 0; i < ACH; i++) {
-      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
-      *reinterpret_cast<u32x4*>(As + r * LDK + kc) = ra[i];
+      int c = tid + i * 256, r = c / CPR;
+      *reinterpret_cast<u32x4*>(As + r * LDK + slot(r, c % CPR) * VEC) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < BCH; i++) {
-      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
-      *reinterpret_cast<u32x4*>(Bs + r * LDK + kc) = rb[i];
+      int c = tid + i * 256, r = c / CPR;
+      *reinterpret_cast<u32x4*>(Bs + r * LDK + slot(r, c % CPR) * VEC) = rb[i];
     }
   };
 
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
   sstore(0);
   __syncthreads();
   int buf = 0;
-  const int lrow = lane & 15, lk = (lane >> 4) * VEC;
+  const int lrow = lane & 15, lg = lane >> 4;
   for (int kt = 0; kt < nk; kt++) {
     if (kt + 1 < nk) gload((kt + 1) * BK);
     const T* As = smem + buf * STAGE + (wm * WM) * LDK;
@@ -105,9 +114,11 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
     for (int ks = 0; ks < BK; ks += KSUB) {
       u32x4 af[MI], bfr[NI];
 #pragma unroll
-      for (int i = 0; i < MI; i++) af[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + ks + lk);
+      for (int i = 0; i < MI; i++)
+        af[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + slot(lrow, ks / VEC + lg) * VEC);
 #pragma unroll
-      for (int j = 0; j < NI; j++) bfr[j] = *reinterpret_cast<const u32x4*>(Bs + (j * 16 + lrow) * LDK + ks + lk);
+      for (int j = 0; j < NI; j++)
+        bfr[j] = *reinterpret_cast<const u32x4*>(Bs + (j * 16 + lrow) * LDK + slot(lrow, ks / VEC + lg) * VEC);
       if constexpr (sizeof(T) == 4) {
 #pragma unroll
         for (int t = 0; t < 4; t++)
@@ -172,24 +183,29 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
 
 // ------------------------------------------------------------------ tile table
 struct TileCfg {
-  int BM, BN, BK, WM, WN;
+  int BM, BN, BK, WM, WN, SWZ;
   const char* name;
 };
 static const TileCfg kF32Tiles[] = {
-    {128, 128, 32, 64, 64, "f32_128x128x32_w64x64"},
-    {64, 128, 32, 32, 64, "f32_64x128x32_w32x64"},
-    {128, 64, 32, 64, 32, "f32_128x64x32_w64x32"},
+    {128, 128, 32, 64, 64, 0, "f32_128x128x32_w64x64"},
+    {64, 128, 32, 32, 64, 0, "f32_64x128x32_w32x64"},
+    {128, 64, 32, 64, 32, 0, "f32_128x64x32_w64x32"},
+    {128, 128, 32, 64, 64, 1, "f32_128x128x32_w64x64_swz1"},
 };
 static const TileCfg kBf16Tiles[] = {
-    {128, 128, 64, 64, 64, "bf16_128x128x64_w64x64"},
-    {256, 128, 64, 128, 64, "bf16_256x128x64_w128x64"},
-    {128, 256, 64, 64, 128, "bf16_128x256x64_w64x128"},
-    {64, 128, 64, 32, 64, "bf16_64x128x64_w32x64"},
-    {256, 256, 64, 128, 128, "bf16_256x256x64_w128x128"},
-    {256, 256, 32, 128, 128, "bf16_256x256x32_w128x128"},
+    {128, 128, 64, 64, 64, 0, "bf16_128x128x64_w64x64"},
+    {256, 128, 64, 128, 64, 0, "bf16_256x128x64_w128x64"},
+    {128, 256, 64, 64, 128, 0, "bf16_128x256x64_w64x128"},
+    {64, 128, 64, 32, 64, 0, "bf16_64x128x64_w32x64"},
+    {256, 256, 64, 128, 128, 0, "bf16_256x256x64_w128x128"},
+    {256, 256, 32, 128, 128, 0, "bf16_256x256x32_w128x128"},
+    {128, 128, 64, 64, 64, 1, "bf16_128x128x64_w64x64_swz1"},
+    {128, 128, 64, 64, 64, 2, "bf16_128x128x64_w64x64_swz2"},
+    {256, 256, 64, 128, 128, 1, "bf16_256x256x64_w128x128_swz1"},
+    {256, 128, 64, 128, 64, 1, "bf16_256x128x64_w128x64_swz1"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 3 : 6; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 10; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -203,11 +219,11 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
   return true;
 }
 
-template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN>
+template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
-  size_t lds = 2 * (size_t)(BM + BN) * (BK + 16 / sizeof(T)) * sizeof(T);
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI>;
+  size_t lds = 2 * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -223,18 +239,23 @@ template <typename T, typename TO, int EPI>
 static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
     switch (tile) {
-      case 0: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64>(A, B, C, s, st);
-      case 1: return launch_t<T, TO, EPI, 64, 128, 32, 32, 64>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 128, 64, 32, 64, 32>(A, B, C, s, st);
+      case 0: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64, 0>(A, B, C, s, st);
+      case 1: return launch_t<T, TO, EPI, 64, 128, 32, 32, 64, 0>(A, B, C, s, st);
+      case 2: return launch_t<T, TO, EPI, 128, 64, 32, 64, 32, 0>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64, 1>(A, B, C, s, st);
     }
   } else {
     switch (tile) {
-      case 0: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64>(A, B, C, s, st);
-      case 1: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64>(A, B, C, s, st);
-      case 2: return launch_t<T, TO, EPI, 128, 256, 64, 64, 128>(A, B, C, s, st);
-      case 3: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64>(A, B, C, s, st);
-      case 4: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 256, 256, 32, 128, 128>(A, B, C, s, st);
+      case 0: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 0>(A, B, C, s, st);
+      case 1: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 0>(A, B, C, s, st);
+      case 2: return launch_t<T, TO, EPI, 128, 256, 64, 64, 128, 0>(A, B, C, s, st);
+      case 3: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64, 0>(A, B, C, s, st);
+      case 4: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 0>(A, B, C, s, st);
+      case 5: return launch_t<T, TO, EPI, 256, 256, 32, 128, 128, 0>(A, B, C, s, st);
+      case 6: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 1>(A, B, C, s, st);
+      case 7: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 2>(A, B, C, s, st);
+      case 8: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 1>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 1>(A, B, C, s, st);
     }
   }
 }
