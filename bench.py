@@ -115,6 +115,7 @@ def main():
     result = {}
     # ------------------------------------------------------------------ BF16 path
     mb = K.kvop_model_create(cfg, flat, K.KVOP_BF16)
+    tune_report = autotune(K, mb, [n * 32, 60000, n], "bf16")
     proxy = None
     if not args.no_proxy:
         proxy, proxy_info = train_proxy(K, synth, mb, shape, wl.suffix, args, dev)
@@ -167,6 +168,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         mf = K.kvop_model_create(cfg, flat, K.KVOP_F32)
+        tune_report += autotune(K, mf, [n * 32, 60000, n], "f32")
         probe = K.kvop_pool_create(mf, K.KVOP_KV_F32, 1 << 20)
         sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
         K.kvop_pool_destroy(probe)
@@ -231,6 +233,7 @@ def main():
         "roofline": roofline,
         "roofline_attention": roof_att,
         "kernel_ms_per_step": {k: round(v[0], 3) for k, v in prof.items()},
+        "gemm_tiles": tune_report,
         "bf16_plain_tuples_per_s": plain_value,
         "proxy": cascade,
         "per_r": per_r,
@@ -253,6 +256,20 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(json.dumps(line) + "\n")
+
+
+def autotune(K, model, rows_list, tag):
+    """Time every projection tile candidate at the row counts the run uses and keep the
+    fastest (the library's own autotuner); returns the chosen tiles."""
+    chosen = {}
+    for rows in rows_list:
+        rep = K.kvop_autotune(model, rows, 3)
+        for line in rep.splitlines():
+            if line.startswith("best "):
+                _, name, m, tile = line.split()
+                chosen[f"{tag}/{name}/{m}"] = tile
+    log(f"autotune {tag}: {chosen}")
+    return chosen
 
 
 def train_proxy(K, synth, mb, shape, suffix, args, dev):

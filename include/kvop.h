@@ -176,6 +176,40 @@ kvop_status kvop_op_eval_select(kvop_pool* pool, const kvop_op* op, float r, con
                                 const int32_t* select_host, int32_t n_select, void* stream, float* logits_out_dev,
                                 int8_t* decision_out_dev);
 
+/* ---- batching form -----------------------------------------------------------
+ * Mixed operators in one pass (the batched execution of Section 5, "Execution-time
+ * Batching", with variable-length work lists instead of padding): the items of
+ * several filters, joins and at most one map share every projection launch and one
+ * attention launch per layer; the map then continues with its decode steps.
+ *   ops          : n_ops operators with their own output buffers (device):
+ *                  filter/join logits [items of that op, 2] and decisions [items];
+ *                  map logits [items, n_gen, label_n] and tokens [items, n_gen];
+ *                  an operator's outputs are in the order its items appear
+ *   item_op_host : operator index of every item
+ *   item_list_host: first list/handle index of every item (a join uses two
+ *                  consecutive ones); lists and handles as for kvop_op_eval
+ * Work is split into waves of at most kvop_set_wave_rows rows with a fixed number of items
+ * per operator.  KVOP_MIXED_PERSISTENT runs the attention as a persistent launch that
+ * takes (item, kv head) units from a device counter; KVOP_MIXED_GRAPH captures one full
+ * wave's launch sequence in a hipGraph and replays it for the following full waves
+ * (the first and the last, partial wave run directly).  The call synchronises `stream`
+ * to validate the lists, and again at the end when a graph was used.
+ * Errors as kvop_op_eval; EINVAL for more than one map operator. */
+typedef struct kvop_mixed_op {
+  kvop_op op;
+  float* logits_out_dev;
+  int8_t* decision_out_dev;   /* filter/join, nullable */
+  int32_t* tokens_out_dev;    /* map */
+} kvop_mixed_op;
+#define KVOP_MIXED_PERSISTENT 1u
+#define KVOP_MIXED_GRAPH 2u
+/* Suffix rows per wave of kvop_op_eval / kvop_mixed_eval (default 131072; >= 64). */
+kvop_status kvop_set_wave_rows(int64_t rows);
+kvop_status kvop_mixed_eval(kvop_pool* pool, const kvop_mixed_op* ops, int32_t n_ops, float r, const int32_t* idx_dev,
+                            const int64_t* idx_offsets_host, const kvop_handle* handles_host,
+                            const int32_t* item_op_host, const int64_t* item_list_host, int32_t n_items,
+                            uint32_t flags, void* stream);
+
 /* ---- learned proxy ----------------------------------------------------------
  * The cheap first stage of a two-stage cascade (Section 4.1, Eqs. 1-3: an operator
  * accepts or rejects a tuple, or passes it on as unsure).  Network:
@@ -228,6 +262,18 @@ kvop_status kvop_profile_start(void);
 kvop_status kvop_profile_stop(double* ms_out, int64_t* count_out, int32_t n);
 int32_t kvop_profile_num_classes(void);
 const char* kvop_profile_class_name(int32_t i);
+/* Autotuner: for each projection of the model (QKV, O, gate/up, down) at M = rows, time
+ * every tile candidate (reps launches each, HIP events on `stream`) and record the fastest
+ * in the tuning table used by kv_build / op_eval for that (dtype, epilogue, N, K, M bucket
+ * = floor(log2 M)).  Allocates temporary scratch; synchronises.  A text report of every
+ * timing is written to report (nullable, report_len bytes incl. the terminator). */
+kvop_status kvop_autotune(kvop_model* model, int64_t rows, int32_t reps, void* stream, char* report,
+                          int32_t report_len);
+/* The tuning table as text lines "dtype epilogue N K mbucket tile_name"; returns the full
+ * length (write at most len-1 bytes + terminator into buf, which may be NULL). */
+int32_t kvop_tuning_export(char* buf, int32_t len);
+/* Load lines in the export format into the tuning table (EINVAL if a line is not understood). */
+kvop_status kvop_tuning_import(const char* text);
 /* Record the best tile for (dtype, epilogue, N, K, M) in the library's tuning table
  * (used by later kvop_kv_build / kvop_op_eval calls). */
 kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epilogue, int32_t N, int32_t K, int32_t M, int32_t tile);

@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kRopeMaxPos = 65536;
 constexpr int64_t kAlign = 256;
+int64_t g_wave_rows = 131072;  // suffix rows per op_eval / mixed wave
 
 // ---- optional per-kernel-class timing: HIP events recorded on the caller's stream around
 // each launch while profiling is on; read back (synchronising) by kvop_profile_stop.
@@ -32,6 +33,7 @@ const char* kProfNames[PC_COUNT] = {"gemm_qkv", "gemm_o", "gemm_gate_up", "gemm_
                                     "rmsnorm", "embed", "head", "other"};
 struct Prof {
   bool on = false;
+  bool capturing = false;  // no event records while a graph is being captured
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   double ms[PC_COUNT] = {};
@@ -49,7 +51,7 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(int k_, hipStream_t st_) : k(k_), st(st_) {
-    if (g_prof.on) { a = g_prof.get(); b = g_prof.get(); (void)hipEventRecord(a, st); }
+    if (g_prof.on && !g_prof.capturing) { a = g_prof.get(); b = g_prof.get(); (void)hipEventRecord(a, st); }
   }
   ~ProfScope() {
     if (a) { (void)hipEventRecord(b, st); g_prof.pending.push_back({k, {a, b}}); }
@@ -123,8 +125,9 @@ struct kvop_model {
   DevBuf ws;
   DevBuf meta;
   HostStage stage;
-  int* dflag = nullptr;
+  int* dflag = nullptr;   // [0]: list-validation count, [16]: persistent-attention unit counter
   int* hflag = nullptr;
+  int n_cu = 0;
 
   int qkv_cols() const { return (cfg.n_heads + 2 * cfg.n_kv_heads) * cfg.head_dim; }
   int esz() const { return dt == DT_F32 ? 4 : 2; }
@@ -292,7 +295,11 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   a.G = H / Hkv;
   a.pool = pool;
   a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
-  { ProfScope ps(PC_ATTENTION, st); HIPTRY(attention(dt, kvdt, D, a, st)); }
+  {
+    ProfScope ps(PC_ATTENTION, st);
+    if (a.counter) HIPTRY(fill_i32(a.counter, 0, 1, st));
+    HIPTRY(attention(dt, kvdt, D, a, st));
+  }
   // rows continuing: all, or a strided selection (last row of each item)
   const int n = lp.n_sel;
   const int64_t sa = (int64_t)lp.sel_stride;
@@ -452,7 +459,13 @@ kvop_status kvop_model_create(const kvop_model_cfg* cfg, const float* w, int64_t
     if (hipMemcpyAsync(m->sin_tab, sn.data(), sn.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) st_ok = KVOP_EDEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) st_ok = KVOP_EDEVICE;
   }
-  if (hipMalloc((void**)&m->dflag, 64) != hipSuccess || hipHostMalloc((void**)&m->hflag, 64, 0) != hipSuccess) {
+  {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (m->n_cu <= 0) m->n_cu = 256;
+  }
+  if (hipMalloc((void**)&m->dflag, 256) != hipSuccess || hipHostMalloc((void**)&m->hflag, 64, 0) != hipSuccess) {
     delete m;
     return fail(KVOP_ENOMEM, "flag allocation");
   }
@@ -757,7 +770,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
   const int qc = m->qkv_cols();
   const int Pmax_s = std::max(1, std::min(S, 64 / G));       // query positions per work item
   const int wq = (S + Pmax_s - 1) / Pmax_s;                  // work items per operator item
-  const int64_t max_rows = 131072;
+  const int64_t max_rows = g_wave_rows;
   const int wave_items = (int)std::max<int64_t>(1, max_rows / S);
   const int rows_per_item = S + (kind == KVOP_MAP ? n_gen - 1 : 0);  // own rows kept for decoding
   const int e = m->esz();
@@ -918,7 +931,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     if (kind != KVOP_MAP) {
       ProfScope ps(PC_HEAD, st);
       HIPTRY(head_filter(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->yes_id, op->no_id,
-                         op->theta_pos, op->theta_neg, (const int32_t*)(md + o_out), logits, decision, st));
+                         op->theta_pos, op->theta_neg, nullptr, (const int32_t*)(md + o_out), logits, decision, st));
       continue;
     }
     // ---- map: step 1 from the suffix's last row, then n_gen - 1 decode steps
@@ -927,7 +940,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     float* lg = logits;
     int32_t* tk = tokens_out;
     const int32_t* orow = (const int32_t*)(md + o_out);
-    HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, orow, lg,
+    HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, nullptr, orow, lg,
                     (int64_t)n_gen * ln, tk, n_gen, ntok, st));
     for (int t = 1; t < n_gen; t++) {
       // positions of the fed token: L + S + t - 1; it is own row S + t - 1 of its item
@@ -1009,7 +1022,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
           HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, s), bufs.act, W.wdown, bufs.x, s, st));
         }
       }
-      HIPTRY(head_map(m->dt, bufs.x, d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, orow,
+      HIPTRY(head_map(m->dt, bufs.x, d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, nullptr, orow,
                       lg + (int64_t)t * ln, (int64_t)n_gen * ln, tk + t, n_gen, ntok, st));
     }
   }
@@ -1029,6 +1042,489 @@ kvop_status kvop_op_eval_select(kvop_pool* p, const kvop_op* op, float r, const 
   if (!select_host && n_select > 0) return fail(KVOP_EINVAL, "null selection");
   if (n_select == 0) return KVOP_OK;
   return op_eval_impl(p, op, r, idx, idx_offsets, hs, n_items, select_host, n_select, stream, logits, decision, nullptr);
+}
+
+// ------------------------------------------------------------------ mixed operators (batching form)
+namespace {
+
+struct MixedWave {
+  std::vector<std::vector<int>> items;  // per op: item ids of this wave
+  int64_t rows = 0;
+};
+
+}  // namespace
+
+kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_ops, float r, const int32_t* idx,
+                            const int64_t* idx_off, const kvop_handle* hs, const int32_t* item_op,
+                            const int64_t* item_list, int32_t n_items, uint32_t flags, void* stream) {
+  if (!p || !ops || n_ops < 1 || n_items < 0 || (n_items > 0 && (!item_op || !item_list || !idx || !idx_off || !hs)))
+    return fail(KVOP_EINVAL, "bad arguments");
+  if (n_items == 0) return KVOP_OK;
+  if (!(r > 0.f && r <= 1.f)) return fail(KVOP_EINVAL, "retention must be in (0, 1]");
+  kvop_model* m = p->m;
+  const kvop_model_cfg& c = m->cfg;
+  hipStream_t st = (hipStream_t)stream;
+  int map_op = -1;
+  bool any_join = false;
+  for (int k = 0; k < n_ops; k++) {
+    const kvop_op& o = ops[k].op;
+    if (o.kind != KVOP_FILTER && o.kind != KVOP_MAP && o.kind != KVOP_JOIN) return fail(KVOP_EINVAL, "bad op kind");
+    if (o.suffix_len < 1 || !o.suffix_host) return fail(KVOP_EINVAL, "empty suffix");
+    for (int j = 0; j < o.suffix_len; j++)
+      if (o.suffix_host[j] < 0 || o.suffix_host[j] >= c.vocab) return fail(KVOP_EINVAL, "suffix id out of range");
+    if (!ops[k].logits_out_dev) return fail(KVOP_EINVAL, "null output");
+    if (o.kind == KVOP_MAP) {
+      if (map_op >= 0) return fail(KVOP_EINVAL, "at most one map operator per mixed call");
+      if (o.n_gen < 1 || o.label_n < 1 || o.label_lo < 0 || o.label_lo + o.label_n > c.vocab || !ops[k].tokens_out_dev)
+        return fail(KVOP_EINVAL, "bad map fields");
+      map_op = k;
+    } else if (o.yes_id < 0 || o.yes_id >= c.vocab || o.no_id < 0 || o.no_id >= c.vocab) {
+      return fail(KVOP_EINVAL, "bad answer ids");
+    }
+    if (o.kind == KVOP_JOIN) any_join = true;
+  }
+  // items per operator, output rank of every item, list checks
+  std::vector<std::vector<int>> by_op(n_ops);
+  std::vector<int32_t> rank(n_items);
+  std::vector<const DocSlot*> docA(n_items), docB(n_items, nullptr);
+  std::vector<ListCheck> checks;
+  for (int i = 0; i < n_items; i++) {
+    int k = item_op[i];
+    if (k < 0 || k >= n_ops) return fail(KVOP_EINVAL, "item operator out of range");
+    rank[i] = (int32_t)by_op[k].size();
+    by_op[k].push_back(i);
+    const kvop_op& o = ops[k].op;
+    const int nl = o.kind == KVOP_JOIN ? 2 : 1;
+    for (int j = 0; j < nl; j++) {
+      const int64_t li = item_list[i] + j;
+      if (li < 0) return fail(KVOP_EINVAL, "negative list index");
+      const DocSlot* d = lookup(p, hs[li]);
+      if (!d) return fail(KVOP_EBADHANDLE, "handle " + std::to_string(li) + " is not live in this pool");
+      int64_t kk = idx_off[li + 1] - idx_off[li];
+      if (kk < 1 || kk > d->L) return fail(KVOP_EINVAL, "list " + std::to_string(li) + " has a bad length");
+      if (!(o.flags & KVOP_FLAG_ANY_COUNT) && kk != retained_count(r, d->L))
+        return fail(KVOP_EINVAL, "list " + std::to_string(li) + " does not hold k(r, L) rows");
+      checks.push_back(ListCheck{idx_off[li], (int32_t)kk, d->L});
+      (j == 0 ? docA[i] : docB[i]) = d;
+    }
+    int64_t top = docA[i]->L + (docB[i] ? docB[i]->L : 0);
+    if (top + o.suffix_len + (o.kind == KVOP_MAP ? o.n_gen : 1) >= kRopeMaxPos)
+      return fail(KVOP_EINVAL, "positions exceed the rotary table");
+  }
+  {
+    Mirror mir;
+    size_t o_chk = mir.add(checks.size() * sizeof(ListCheck));
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+      return fail(KVOP_ENOMEM, "metadata staging");
+    memcpy(m->stage.p + o_chk, checks.data(), checks.size() * sizeof(ListCheck));
+    HIPTRY(hipMemcpyAsync(m->meta.p, m->stage.p, mir.size, hipMemcpyHostToDevice, st));
+    HIPTRY(fill_i32(m->dflag, 0, 1, st));
+    HIPTRY(validate_lists(idx, (const ListCheck*)m->meta.p, (int)checks.size(), m->dflag, st));
+    HIPTRY(hipMemcpyAsync(m->hflag, m->dflag, 4, hipMemcpyDeviceToHost, st));
+    HIPTRY(hipStreamSynchronize(st));
+    if (m->hflag[0] != 0)
+      return fail(KVOP_EINVAL, std::to_string(m->hflag[0]) + " index list(s) unsorted or out of range");
+  }
+
+  const int d = c.d_model, H = c.n_heads, Hkv = c.n_kv_heads, D = c.head_dim, G = H / Hkv, F = c.d_ffn;
+  const int qc = m->qkv_cols();
+  const int e = m->esz();
+  const int64_t own_ld = 2LL * Hkv * D;
+  // waves with a fixed per-operator composition: c_k items of operator k per wave
+  int64_t total_rows = 0;
+  for (int k = 0; k < n_ops; k++) total_rows += (int64_t)by_op[k].size() * ops[k].op.suffix_len;
+  const int64_t max_rows = g_wave_rows;
+  const int W = (int)std::max<int64_t>(1, (total_rows + max_rows - 1) / max_rows);
+  std::vector<int> per(n_ops);
+  for (int k = 0; k < n_ops; k++) per[k] = (int)((by_op[k].size() + W - 1) / W);
+  const bool use_graph = (flags & KVOP_MIXED_GRAPH) != 0;
+  const bool persistent = (flags & KVOP_MIXED_PERSISTENT) != 0;
+  int* counter = m->dflag + 16;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  auto cleanup_graph = [&]() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  };
+  size_t full_meta = 0;
+
+  for (int w = 0; w < W; w++) {
+    // ---- items of this wave, rows grouped by operator
+    std::vector<int> blk_row(n_ops), blk_n(n_ops);
+    int64_t rows = 0;
+    bool full = true;
+    for (int k = 0; k < n_ops; k++) {
+      int a = std::min<int>((int)by_op[k].size(), w * per[k]), b = std::min<int>((int)by_op[k].size(), (w + 1) * per[k]);
+      blk_row[k] = (int)rows;
+      blk_n[k] = b - a;
+      if (b - a != per[k]) full = false;
+      rows += (int64_t)(b - a) * ops[k].op.suffix_len;
+    }
+    if (rows == 0) continue;
+    auto item_at = [&](int k, int b) { return by_op[k][(size_t)w * per[k] + b]; };
+    std::vector<int32_t> tok(rows), pos(rows), shift(any_join ? rows : 0, -1);
+    std::vector<AttnWork> work;
+    std::vector<std::vector<int32_t>> in_rows(n_ops), out_rows(n_ops);
+    int Pmax = 64;
+    for (int k = 0; k < n_ops; k++) Pmax = std::min(Pmax, std::max(1, std::min(ops[k].op.suffix_len, 64 / G)));
+    for (int k = 0; k < n_ops; k++) {
+      const kvop_op& o = ops[k].op;
+      const int S = o.suffix_len;
+      for (int b = 0; b < blk_n[k]; b++) {
+        const int it = item_at(k, b);
+        const DocSlot* A = docA[it];
+        const DocSlot* Bd = docB[it];
+        const int64_t r0 = blk_row[k] + (int64_t)b * S;
+        const int pos0 = A->L + (Bd ? Bd->L : 0);
+        for (int j = 0; j < S; j++) {
+          tok[r0 + j] = o.suffix_host[j];
+          pos[r0 + j] = pos0 + j;
+          if (any_join) shift[r0 + j] = Bd ? A->L : -1;
+        }
+        for (int q0 = 0; q0 < S; q0 += Pmax) {
+          AttnWork wk{};
+          const int64_t la = item_list[it];
+          wk.off_a = (int64_t)A->off;
+          wk.idx_a = idx_off[la];
+          wk.L_a = A->L;
+          wk.n_a = (int32_t)(idx_off[la + 1] - idx_off[la]);
+          if (Bd) {
+            wk.off_b = (int64_t)Bd->off;
+            wk.idx_b = idx_off[la + 1];
+            wk.L_b = Bd->L;
+            wk.n_b = (int32_t)(idx_off[la + 2] - idx_off[la + 1]);
+          } else {
+            wk.off_b = -1;
+            wk.idx_b = -1;
+          }
+          wk.q_row0 = (int32_t)(r0 + q0);
+          wk.q_pos0 = pos0 + q0;
+          wk.n_q = std::min(Pmax, S - q0);
+          wk.own_row0 = (int32_t)r0;
+          wk.n_own = std::min(S, q0 + Pmax);
+          wk.own_pos0 = pos0;
+          work.push_back(wk);
+        }
+        in_rows[k].push_back((int32_t)(r0 + S - 1));
+        out_rows[k].push_back(rank[it]);
+      }
+    }
+    std::stable_sort(work.begin(), work.end(),
+                     [](const AttnWork& a, const AttnWork& b) { return a.n_a + a.n_b > b.n_a + b.n_b; });
+    // map decode metadata for every step
+    const int nm = map_op >= 0 ? blk_n[map_op] : 0;
+    const int n_gen = map_op >= 0 ? ops[map_op].op.n_gen : 1;
+    const int Sm = map_op >= 0 ? ops[map_op].op.suffix_len : 0;
+    const int rpi = Sm + n_gen - 1;
+    std::vector<int32_t> own_src, own_dst, dec_src, pdec, ddst;
+    std::vector<AttnWork> dwork;
+    if (nm > 0) {
+      for (int b = 0; b < nm; b++) {
+        dec_src.push_back(b);
+        for (int j = 0; j < Sm; j++) {
+          own_src.push_back(blk_row[map_op] + b * Sm + j);
+          own_dst.push_back(b * rpi + j);
+        }
+      }
+      for (int t = 1; t < n_gen; t++)
+        for (int b = 0; b < nm; b++) {
+          const int it = item_at(map_op, b);
+          const DocSlot* A = docA[it];
+          pdec.push_back(A->L + Sm + t - 1);
+          ddst.push_back(b * rpi + Sm + t - 1);
+          AttnWork wk{};
+          wk.off_a = (int64_t)A->off;
+          wk.off_b = -1;
+          wk.idx_a = idx_off[item_list[it]];
+          wk.idx_b = -1;
+          wk.L_a = A->L;
+          wk.n_a = (int32_t)(idx_off[item_list[it] + 1] - idx_off[item_list[it]]);
+          wk.q_row0 = b;
+          wk.q_pos0 = A->L + Sm + t - 1;
+          wk.n_q = 1;
+          wk.own_row0 = b * rpi;
+          wk.n_own = Sm + t;
+          wk.own_pos0 = A->L;
+          dwork.push_back(wk);
+        }
+    }
+    // ---- metadata layout (identical for every full wave)
+    Mirror mir;
+    const size_t o_tok = mir.add(rows * 4), o_pos = mir.add(rows * 4), o_shift = mir.add(shift.size() * 4),
+                 o_work = mir.add(work.size() * sizeof(AttnWork));
+    std::vector<size_t> o_in(n_ops), o_out(n_ops);
+    for (int k = 0; k < n_ops; k++) {
+      o_in[k] = mir.add(in_rows[k].size() * 4);
+      o_out[k] = mir.add(out_rows[k].size() * 4);
+    }
+    const size_t o_os = mir.add(own_src.size() * 4), o_od = mir.add(own_dst.size() * 4),
+                 o_ds = mir.add(dec_src.size() * 4), o_pd = mir.add(pdec.size() * 4), o_dd = mir.add(ddst.size() * 4),
+                 o_dw = mir.add(dwork.size() * sizeof(AttnWork)), o_ntok = mir.add(nm * 4);
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+      return fail(KVOP_ENOMEM, "metadata staging");
+    char* hp = m->stage.p;
+    auto put = [&](size_t o, const void* src, size_t n) { if (n) memcpy(hp + o, src, n); };
+    put(o_tok, tok.data(), rows * 4);
+    put(o_pos, pos.data(), rows * 4);
+    put(o_shift, shift.data(), shift.size() * 4);
+    put(o_work, work.data(), work.size() * sizeof(AttnWork));
+    for (int k = 0; k < n_ops; k++) {
+      put(o_in[k], in_rows[k].data(), in_rows[k].size() * 4);
+      put(o_out[k], out_rows[k].data(), out_rows[k].size() * 4);
+    }
+    put(o_os, own_src.data(), own_src.size() * 4);
+    put(o_od, own_dst.data(), own_dst.size() * 4);
+    put(o_ds, dec_src.data(), dec_src.size() * 4);
+    put(o_pd, pdec.data(), pdec.size() * 4);
+    put(o_dd, ddst.data(), ddst.size() * 4);
+    put(o_dw, dwork.data(), dwork.size() * sizeof(AttnWork));
+    const size_t act = act_bytes(m, rows, any_join);
+    const size_t own_bytes = (size_t)c.n_layers * nm * rpi * own_ld * e;
+    if (m->ws.reserve(act + align_up(own_bytes, kAlign), st) != hipSuccess) return fail(KVOP_ENOMEM, "activation workspace");
+    char* md = (char*)m->meta.p;
+    HIPTRY(hipMemcpyAsync(md, hp, o_ntok, hipMemcpyHostToDevice, st));
+    HIPTRY(hipEventRecord(m->stage.ev, st));
+    m->stage.pending = true;
+    LayerBufs bufs = carve(m, (char*)m->ws.p, rows, any_join);
+    char* ownbuf = (char*)m->ws.p + act;
+
+    // ---- the wave's launch sequence (enqueued directly, or captured once and replayed)
+    auto enqueue = [&]() -> kvop_status {
+      HIPTRY(embed_rows(m->dt, m->embed, (const int32_t*)(md + o_tok), (int)rows, d, c.vocab, bufs.x, st));
+      LayerPlan lp{};
+      lp.rows = (int)rows;
+      lp.pos = (const int32_t*)(md + o_pos);
+      lp.alt_shift = any_join ? (const int32_t*)(md + o_shift) : nullptr;
+      lp.attn.work = (const AttnWork*)(md + o_work);
+      lp.attn.n_work = (int)work.size();
+      lp.attn.idx = idx;
+      lp.attn.Pmax = Pmax;
+      lp.attn.counter = persistent ? counter : nullptr;
+      lp.attn.persistent_wgs = 2 * m->n_cu;
+      lp.own_from_qkv = true;
+      lp.n_sel = (int)rows;  // every row continues (operators read different last rows)
+      lp.sel_stride = 1;
+      lp.sel_off = 0;
+      for (int l = 0; l < c.n_layers; l++) {
+        kvop_status s = run_layer(m, l, bufs, lp, p->base, p->kvdt, nullptr, 0, st);
+        if (s != KVOP_OK) return s;
+        if (nm > 0)
+          HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_os),
+                              (const int32_t*)(md + o_od), nm * Sm, ownbuf + (size_t)l * nm * rpi * own_ld * e, own_ld,
+                              st));
+      }
+      for (int k = 0; k < n_ops; k++) {
+        const kvop_op& o = ops[k].op;
+        if (o.kind == KVOP_MAP || blk_n[k] == 0) continue;
+        HIPTRY(head_filter(m->dt, bufs.x, d, blk_n[k], d, m->final_norm, c.rms_eps, m->head, o.yes_id, o.no_id,
+                           o.theta_pos, o.theta_neg, (const int32_t*)(md + o_in[k]), (const int32_t*)(md + o_out[k]),
+                           ops[k].logits_out_dev, ops[k].decision_out_dev, st));
+      }
+      if (nm == 0) return KVOP_OK;
+      const kvop_op& o = ops[map_op].op;
+      const int ln = o.label_n;
+      int32_t* ntok = (int32_t*)(md + o_ntok);
+      const int32_t* orow = (const int32_t*)(md + o_out[map_op]);
+      HIPTRY(head_map(m->dt, bufs.x, d, nm, d, m->final_norm, c.rms_eps, m->head, o.label_lo, ln,
+                      (const int32_t*)(md + o_in[map_op]), orow, ops[map_op].logits_out_dev, (int64_t)n_gen * ln,
+                      ops[map_op].tokens_out_dev, n_gen, ntok, st));
+      for (int t = 1; t < n_gen; t++) {
+        const int32_t* pd = (const int32_t*)(md + o_pd) + (size_t)(t - 1) * nm;
+        const int32_t* dd = (const int32_t*)(md + o_dd) + (size_t)(t - 1) * nm;
+        const AttnWork* dw = (const AttnWork*)(md + o_dw) + (size_t)(t - 1) * nm;
+        HIPTRY(embed_rows(m->dt, m->embed, ntok, nm, d, c.vocab, bufs.x, st));
+        for (int l = 0; l < c.n_layers; l++) {
+          char* own_l = ownbuf + (size_t)l * nm * rpi * own_ld * e;
+          const kvop_model::Layer& Wl = m->layers[l];
+          HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, Wl.attn_norm, nm, d, c.rms_eps, bufs.h, d, st));
+          {
+            GemmShape g{nm, qc, d, d, d, qc};
+            HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, g), bufs.h, Wl.wqkv, bufs.qkv, g, st));
+          }
+          HIPTRY(rope_qk(m->dt, bufs.qkv, qc, nm, H, Hkv, D, pd, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
+          HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_ds), dd, nm, own_l,
+                              own_ld, st));
+          AttnArgs a{};
+          a.work = dw;
+          a.n_work = nm;
+          a.idx = idx;
+          a.pool = p->base;
+          a.q = bufs.qkv;
+          a.q_stride = qc;
+          a.own = own_l;
+          a.own_stride = own_ld;
+          a.own_kcol = 0;
+          a.own_vcol = Hkv * D;
+          a.out = bufs.attn;
+          a.out_stride = H * D;
+          a.layer = l;
+          a.n_layers = c.n_layers;
+          a.Hkv = Hkv;
+          a.G = G;
+          a.Pmax = 1;
+          a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
+          a.counter = persistent ? counter : nullptr;
+          a.persistent_wgs = 2 * m->n_cu;
+          if (a.counter) HIPTRY(fill_i32(a.counter, 0, 1, st));
+          HIPTRY(attention(m->dt, p->kvdt, D, a, st));
+          {
+            GemmShape g{nm, d, H * D, H * D, H * D, d};
+            HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, g), bufs.attn, Wl.wo, bufs.x, g, st));
+          }
+          HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, Wl.ffn_norm, nm, d, c.rms_eps, bufs.h, d, st));
+          {
+            GemmShape g{nm, 2 * F, d, d, d, F};
+            HIPTRY(gemm(m->dt, m->dt, EPI_SWIGLU, gemm_pick_tile(m->dt, EPI_SWIGLU, g), bufs.h, Wl.wgu, bufs.act, g, st));
+          }
+          {
+            GemmShape g{nm, d, F, F, F, d};
+            HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, g), bufs.act, Wl.wdown, bufs.x, g, st));
+          }
+        }
+        HIPTRY(head_map(m->dt, bufs.x, d, nm, d, m->final_norm, c.rms_eps, m->head, o.label_lo, ln, nullptr, orow,
+                        ops[map_op].logits_out_dev + (int64_t)t * ln, (int64_t)n_gen * ln, ops[map_op].tokens_out_dev + t,
+                        n_gen, ntok, st));
+      }
+      return KVOP_OK;
+    };
+
+    // the first wave always runs directly (it also sizes every buffer); later full waves
+    // replay one captured graph when asked to
+    const bool graph_wave = use_graph && full && w > 0;
+    if (!graph_wave) {
+      kvop_status s = enqueue();
+      if (s != KVOP_OK) { cleanup_graph(); return s; }
+      if (full) full_meta = mir.size;
+      continue;
+    }
+    if (!gexec) {
+      if (mir.size != full_meta) { cleanup_graph(); return fail(KVOP_EDEVICE, "wave layout changed"); }
+      g_prof.capturing = true;
+      hipError_t ce = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+      kvop_status s = ce == hipSuccess ? enqueue() : fail(KVOP_EDEVICE, "hipStreamBeginCapture failed");
+      hipError_t ee = hipStreamEndCapture(st, &graph);
+      g_prof.capturing = false;
+      if (s != KVOP_OK) { cleanup_graph(); return s; }
+      if (ee != hipSuccess) { cleanup_graph(); return fail(KVOP_EDEVICE, "hipStreamEndCapture failed"); }
+      if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        cleanup_graph();
+        return fail(KVOP_EDEVICE, "hipGraphInstantiate failed");
+      }
+    }
+    if (hipGraphLaunch(gexec, st) != hipSuccess) {
+      cleanup_graph();
+      return fail(KVOP_EDEVICE, "hipGraphLaunch failed");
+    }
+  }
+  if (gexec) {
+    if (hipStreamSynchronize(st) != hipSuccess) { cleanup_graph(); return fail(KVOP_EDEVICE, "graph replay failed"); }
+  }
+  cleanup_graph();
+  return KVOP_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+kvop_status kvop_autotune(kvop_model* m, int64_t rows, int32_t reps, void* stream, char* report, int32_t report_len) {
+  if (!m || rows < 1 || rows > (1 << 30) || reps < 1) return fail(KVOP_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  const kvop_model_cfg& c = m->cfg;
+  const int dt = m->dt, e = m->esz();
+  const int d = c.d_model, F = c.d_ffn, HD = c.n_heads * c.head_dim, qc = m->qkv_cols();
+  struct Shp { int N, K, epi; const char* name; };
+  const Shp shapes[] = {{qc, d, EPI_STORE, "qkv"}, {d, HD, EPI_ADD, "o"}, {2 * F, d, EPI_SWIGLU, "gate_up"},
+                        {d, F, EPI_ADD, "down"}};
+  const int M = (int)rows;
+  int64_t maxK = std::max(std::max(d, HD), F), maxN = std::max(std::max(qc, d), 2 * F);
+  void *A = nullptr, *B = nullptr, *Cb = nullptr;
+  size_t a_b = (size_t)M * maxK * e, b_b = (size_t)maxN * maxK * e, c_b = (size_t)M * maxN * 4;
+  if (hipMalloc(&A, a_b) != hipSuccess || hipMalloc(&B, b_b) != hipSuccess || hipMalloc(&Cb, c_b) != hipSuccess) {
+    if (A) (void)hipFree(A);
+    if (B) (void)hipFree(B);
+    (void)hipGetLastError();
+    return fail(KVOP_ENOMEM, "autotune scratch");
+  }
+  std::string rep;
+  kvop_status status = KVOP_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipMemsetAsync(A, 0x3c, a_b, st);
+  (void)hipMemsetAsync(B, 0x3c, b_b, st);
+  for (const Shp& sh : shapes) {
+    GemmShape g{M, sh.N, sh.K, sh.K, sh.K, sh.epi == EPI_SWIGLU ? sh.N / 2 : sh.N};
+    const int out_dt = sh.epi == EPI_ADD ? DT_F32 : dt;
+    int best = -1;
+    float best_ms = 1e30f;
+    for (int t = 0; t < gemm_num_tiles(dt); t++) {
+      if (!gemm_tile_ok(dt, t, g, sh.epi)) continue;
+      if (gemm(dt, out_dt, sh.epi, t, A, B, Cb, g, st) != hipSuccess) { status = fail(KVOP_EDEVICE, "autotune launch"); break; }
+      (void)hipEventRecord(e0, st);
+      for (int i = 0; i < reps; i++) (void)gemm(dt, out_dt, sh.epi, t, A, B, Cb, g, st);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) { status = fail(KVOP_EDEVICE, "autotune timing"); break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      rep += std::string(sh.name) + " M=" + std::to_string(M) + " " + gemm_tile_name(dt, t) + " " + std::to_string(ms) +
+             " ms\n";
+      if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    if (status != KVOP_OK) break;
+    if (best >= 0) {
+      gemm_set_tuned(dt, sh.epi, sh.N, sh.K, gemm_mbucket(M), best);
+      rep += std::string("best ") + sh.name + " M=" + std::to_string(M) + " " + gemm_tile_name(dt, best) + "\n";
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(A);
+  (void)hipFree(B);
+  (void)hipFree(Cb);
+  if (report && report_len > 0) {
+    size_t n = std::min<size_t>(rep.size(), (size_t)report_len - 1);
+    memcpy(report, rep.data(), n);
+    report[n] = 0;
+  }
+  return status;
+}
+
+int32_t kvop_tuning_export(char* buf, int32_t len) {
+  std::string t = gemm_tuned_export();
+  if (buf && len > 0) {
+    size_t n = std::min<size_t>(t.size(), (size_t)len - 1);
+    memcpy(buf, t.data(), n);
+    buf[n] = 0;
+  }
+  return (int32_t)t.size();
+}
+
+kvop_status kvop_tuning_import(const char* text) {
+  if (!text) return fail(KVOP_EINVAL, "null text");
+  std::string s(text);
+  size_t pos = 0;
+  int n_bad = 0;
+  while (pos < s.size()) {
+    size_t nl = s.find('\n', pos);
+    std::string line = s.substr(pos, nl == std::string::npos ? std::string::npos : nl - pos);
+    pos = nl == std::string::npos ? s.size() : nl + 1;
+    if (line.empty()) continue;
+    int dt, epi, N, K, mb;
+    char name[128];
+    if (sscanf(line.c_str(), "%d %d %d %d %d %127s", &dt, &epi, &N, &K, &mb, name) != 6 ||
+        !gemm_tuned_import_line(dt, epi, N, K, mb, name))
+      n_bad++;
+  }
+  if (n_bad) return fail(KVOP_EINVAL, std::to_string(n_bad) + " tuning line(s) not understood");
+  return KVOP_OK;
+}
+
+kvop_status kvop_set_wave_rows(int64_t rows) {
+  if (rows < 64) return fail(KVOP_EINVAL, "wave must hold at least 64 rows");
+  g_wave_rows = rows;
+  return KVOP_OK;
 }
 
 // ------------------------------------------------------------------ profiling

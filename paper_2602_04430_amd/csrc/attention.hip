@@ -17,6 +17,7 @@
 // in LDS.  BF16 path: v_mfma_f32_16x16x32_bf16 with V stored transposed in LDS; FP8
 // (E4M3) cache rows are widened to BF16 exactly while staging and their per-16-row FP32
 // block scales are applied to the scores (K) and to the probabilities (V).
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -175,23 +176,34 @@ struct TileStage {
   }
 };
 
+template <typename TC, int D>
+struct AttnSmem {
+  using C = AttnCfg<TC, D>;
+  __attribute__((aligned(16))) TC Ks[C::KS_ELEMS];
+  __attribute__((aligned(16))) TC Vs[C::VS_ELEMS];
+  float ksc_s[C::KT], vsc_s[C::KT];
+  int kpos_s[C::KT];
+};
+
+// One (work item, kv head) unit, executed by a whole 256-thread workgroup.
 template <typename TC, typename TKV, int D>
-__global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
+__device__ void attn_unit(const AttnArgs& a, int unit, AttnSmem<TC, D>& sm) {
   using C = AttnCfg<TC, D>;
   constexpr int KT = C::KT;
   constexpr int NB = KT / 16;                    // 16-key blocks per tile
   constexpr int ND = D / 16;                     // 16-wide d blocks of the output
   constexpr bool FP8 = sizeof(TKV) == 1;
-  __shared__ __attribute__((aligned(16))) TC Ks[C::KS_ELEMS];
-  __shared__ __attribute__((aligned(16))) TC Vs[C::VS_ELEMS];
-  __shared__ float ksc_s[KT], vsc_s[KT];
-  __shared__ int kpos_s[KT];
+  TC* Ks = sm.Ks;
+  TC* Vs = sm.Vs;
+  float* ksc_s = sm.ksc_s;
+  float* vsc_s = sm.vsc_s;
+  int* kpos_s = sm.kpos_s;
 
-  // kv head fastest: consecutive workgroups are the heads of one item, so the longest-first
+  // kv head fastest: consecutive units are the heads of one item, so the longest-first
   // order of the work list holds across heads
   const int Hkv = a.Hkv;
-  const int h = blockIdx.x % Hkv;
-  const AttnWork w = a.work[blockIdx.x / Hkv];
+  const int h = unit % Hkv;
+  const AttnWork w = a.work[unit / Hkv];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int qi = lane & 15, g4 = lane >> 4;
   const int r = wave * 16 + qi;
@@ -391,6 +403,7 @@ __global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
   // ---- normalise and store: lane holds O[query qi][d = 16*i + 4*g4 + t]
   float l_tot = l_run + __shfl_xor(l_run, 16, 64);
   l_tot += __shfl_xor(l_tot, 32, 64);
+  __syncthreads();  // LDS reused by the workgroup's next unit
   if (!qvalid) return;
   const float inv = l_tot > 0.f ? 1.f / l_tot : 0.f;
   TC* out = reinterpret_cast<TC*>(a.out) + qrow * a.out_stride + hq * D;
@@ -408,10 +421,40 @@ __global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
   }
 }
 
+// One workgroup per unit.
+template <typename TC, typename TKV, int D>
+__global__ __launch_bounds__(256) void attn_kernel(AttnArgs a) {
+  __shared__ AttnSmem<TC, D> sm;
+  attn_unit<TC, TKV, D>(a, blockIdx.x, sm);
+}
+
+// Persistent form: a fixed grid of workgroups takes units from a device counter (reset to
+// zero by the caller before the launch) in list order until every unit is taken; each
+// workgroup exits once the counter passes the unit count, so the grid always drains.
+template <typename TC, typename TKV, int D>
+__global__ __launch_bounds__(256) void attn_persistent_kernel(AttnArgs a) {
+  __shared__ AttnSmem<TC, D> sm;
+  __shared__ int next;
+  const int total = a.n_work * a.Hkv;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int unit = next;
+    __syncthreads();
+    if (unit >= total) break;
+    attn_unit<TC, TKV, D>(a, unit, sm);
+  }
+}
+
 template <typename TC, typename TKV, int D>
 static hipError_t launch_d(const AttnArgs& a, hipStream_t st) {
-  dim3 grid((unsigned)((int64_t)a.n_work * a.Hkv));
-  hipLaunchKernelGGL((attn_kernel<TC, TKV, D>), grid, dim3(256), 0, st, a);
+  const int64_t units = (int64_t)a.n_work * a.Hkv;
+  if (a.counter) {
+    hipLaunchKernelGGL((attn_persistent_kernel<TC, TKV, D>), dim3((unsigned)std::min<int64_t>(units, a.persistent_wgs)),
+                       dim3(256), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((attn_kernel<TC, TKV, D>), dim3((unsigned)units), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -427,6 +470,7 @@ static hipError_t launch_kv(int D, const AttnArgs& a, hipStream_t st) {
 
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st) {
   if (a.n_work <= 0) return hipSuccess;
+  if (a.counter && a.persistent_wgs < 1) return hipErrorInvalidValue;
   if (a.G * a.Pmax > 64 || a.G < 1 || a.Pmax < 1) return hipErrorInvalidValue;
   if (cdt == DT_F32) {
     if (kvdt != DT_F32) return hipErrorInvalidValue;

@@ -281,11 +281,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void head_filter_kernel(const float* __restrict__ x, int64_t ldx, int d,
                                                           const float* __restrict__ g, float eps,
                                                           const T* __restrict__ W, int yes_id, int no_id, float thp,
-                                                          float thn, const int32_t* __restrict__ out_rows,
+                                                          float thn, const int32_t* __restrict__ in_rows,
+                                                          const int32_t* __restrict__ out_rows,
                                                           float* __restrict__ logits, int8_t* __restrict__ decision) {
   __shared__ float red[3][4];
   int item = blockIdx.x;
-  const float* xr = x + (int64_t)item * ldx;
+  const float* xr = x + (int64_t)(in_rows ? in_rows[item] : item) * ldx;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float ss = 0.f;
   for (int c = threadIdx.x; c < d; c += 256) ss += xr[c] * xr[c];
@@ -318,15 +319,15 @@ __global__ __launch_bounds__(256) void head_filter_kernel(const float* __restric
 }
 
 hipError_t head_filter(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* out_rows,
-                       float* logits, int8_t* decision, hipStream_t st) {
+                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* in_rows,
+                       const int32_t* out_rows, float* logits, int8_t* decision, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   if (dt == DT_F32)
     hipLaunchKernelGGL(head_filter_kernel<float>, dim3(n_items), dim3(256), 0, st, x, ldx, d, g, eps,
-                       (const float*)head, yes_id, no_id, th_pos, th_neg, out_rows, logits, decision);
+                       (const float*)head, yes_id, no_id, th_pos, th_neg, in_rows, out_rows, logits, decision);
   else
     hipLaunchKernelGGL(head_filter_kernel<bf16_t>, dim3(n_items), dim3(256), 0, st, x, ldx, d, g, eps,
-                       (const bf16_t*)head, yes_id, no_id, th_pos, th_neg, out_rows, logits, decision);
+                       (const bf16_t*)head, yes_id, no_id, th_pos, th_neg, in_rows, out_rows, logits, decision);
   return hipGetLastError();
 }
 
@@ -334,6 +335,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__ x, int64_t ldx, int d,
                                                        const float* __restrict__ g, float eps,
                                                        const T* __restrict__ W, int lo, int n,
+                                                       const int32_t* __restrict__ in_rows,
                                                        const int32_t* __restrict__ out_rows,
                                                        float* __restrict__ logits, int64_t ldl,
                                                        int32_t* __restrict__ tok_out, int64_t ldt,
@@ -342,7 +344,7 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
   __shared__ float red[4];
   __shared__ int redi[4];
   int item = blockIdx.x;
-  const float* xr = x + (int64_t)item * ldx;
+  const float* xr = x + (int64_t)(in_rows ? in_rows[item] : item) * ldx;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float ss = 0.f;
   for (int c = threadIdx.x; c < d; c += 256) ss += xr[c] * xr[c];
@@ -389,16 +391,16 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
 }
 
 hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                    const void* head, int lo, int n, const int32_t* out_rows, float* logits, int64_t ld_logits,
-                    int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st) {
+                    const void* head, int lo, int n, const int32_t* in_rows, const int32_t* out_rows, float* logits,
+                    int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   size_t lds = (size_t)(d + n) * sizeof(float);
   if (dt == DT_F32)
     hipLaunchKernelGGL(head_map_kernel<float>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps, (const float*)head,
-                       lo, n, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
+                       lo, n, in_rows, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
   else
     hipLaunchKernelGGL(head_map_kernel<bf16_t>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps,
-                       (const bf16_t*)head, lo, n, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
+                       (const bf16_t*)head, lo, n, in_rows, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 // kernel body) so that concurrently resident workgroups of one XCD share A and B tiles.
 #include <algorithm>
 #include <map>
+#include <string>
 #include <tuple>
 
 #include "common.h"
@@ -287,6 +288,27 @@ static int mbucket(int M) {
   return b;
 }
 void gemm_set_tuned(int dt, int epi, int N, int K, int mb, int tile) { tuned()[{dt, epi, N, K, mb}] = tile; }
+int gemm_mbucket(int M) { return mbucket(M); }
+
+std::string gemm_tuned_export() {
+  std::string out;
+  for (auto& kv : tuned()) {
+    int dt, epi, N, K, mb;
+    std::tie(dt, epi, N, K, mb) = kv.first;
+    out += std::to_string(dt) + " " + std::to_string(epi) + " " + std::to_string(N) + " " + std::to_string(K) + " " +
+           std::to_string(mb) + " " + gemm_tile_name(dt, kv.second) + "\n";
+  }
+  return out;
+}
+
+bool gemm_tuned_import_line(int dt, int epi, int N, int K, int mb, const std::string& name) {
+  for (int t = 0; t < gemm_num_tiles(dt); t++)
+    if (name == gemm_tile_name(dt, t)) {
+      gemm_set_tuned(dt, epi, N, K, mb, t);
+      return true;
+    }
+  return false;
+}
 
 int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   auto it = tuned().find({dt, epi, s.N, s.K, mbucket(s.M)});

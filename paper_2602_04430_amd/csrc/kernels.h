@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace kvop {
 
 enum Dt { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
@@ -28,6 +30,10 @@ hipError_t gemm(int dt, int out_dt, int epi, int tile, const void* A, const void
 // default tile for a shape (from the tuned table when present)
 int gemm_pick_tile(int dt, int epi, const GemmShape& s);
 void gemm_set_tuned(int dt, int epi, int N, int K, int mbucket, int tile);
+int gemm_mbucket(int M);
+// tuning table as text lines "dtype epilogue N K mbucket tile_name"
+std::string gemm_tuned_export();
+bool gemm_tuned_import_line(int dt, int epi, int N, int K, int mb, const std::string& name);
 
 // ---------------------------------------------------------------- attention
 // One work item = one (query block, key sources) unit; executed for every kv head.
@@ -61,6 +67,8 @@ struct AttnArgs {
   int64_t out_stride;
   int layer, n_layers, Hkv, G, Pmax;
   float scale_log2;    // log2(e) / sqrt(D)
+  int* counter;        // persistent launch: unit counter (zeroed before the launch), else null
+  int persistent_wgs;  // persistent launch: number of workgroups
 };
 // cdt: compute/query dtype (f32 or bf16); kvdt: cache dtype (f32 with f32; bf16/fp8 with bf16)
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st);
@@ -69,6 +77,7 @@ hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st
 // x[row] = embed[tok[row]] (embed in `dt`), FP32 output; ids clamped to [0, V)
 hipError_t embed_rows(int dt, const void* embed, const int32_t* tok, int n_rows, int d, int vocab, float* x,
                       hipStream_t st);
+// embed rows with per-row token ids (tok[row]); ids clamped to [0, V)
 // embed rows whose token is suffix[row % S] (op_eval input)
 hipError_t embed_suffix(int dt, const void* embed, const int32_t* suffix, int S, int n_rows, int d, int vocab,
                         float* x, hipStream_t st);
@@ -99,14 +108,15 @@ hipError_t copy_kv_rows(int dt, const void* qkv, int64_t ld, int kcol, int n_col
 hipError_t pooled_mean(const float* x, int d, const int64_t* row_off, int n_docs, int n_rows, const float* g,
                        float eps, float* inv_scratch, float* pooled, hipStream_t st);
 // filter/join head: y = rmsnorm(x[row_of_item]) * g; logits (yes, no); log-odds decision
-// item i of the launch writes output row out_rows[i]
+// item i of the launch reads row in_rows[i] of x (or row i when in_rows is null) and writes
+// output row out_rows[i]
 hipError_t head_filter(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* out_rows,
-                       float* logits, int8_t* decision, hipStream_t st);
+                       const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* in_rows,
+                       const int32_t* out_rows, float* logits, int8_t* decision, hipStream_t st);
 // map head: logits over [lo, lo+n) and argmax (lowest id on ties)
 hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
-                    const void* head, int lo, int n, const int32_t* out_rows, float* logits, int64_t ld_logits,
-                    int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st);
+                    const void* head, int lo, int n, const int32_t* in_rows, const int32_t* out_rows, float* logits,
+                    int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st);
 // index-list validation: counts lists that are unsorted or out of range into *bad
 struct ListCheck {
   int64_t off;

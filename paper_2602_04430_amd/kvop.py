@@ -21,6 +21,7 @@ KVOP_F32, KVOP_BF16 = 0, 1
 KVOP_KV_F32, KVOP_KV_BF16, KVOP_KV_FP8 = 0, 1, 2
 KVOP_FILTER, KVOP_MAP, KVOP_JOIN = 0, 1, 2
 KVOP_FLAG_ANY_COUNT = 1
+KVOP_MIXED_PERSISTENT, KVOP_MIXED_GRAPH = 1, 2
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBADHANDLE", 4: "EDEVICE"}
 
 
@@ -41,6 +42,11 @@ class kvop_op(C.Structure):
                 ("yes_id", C.c_int32), ("no_id", C.c_int32), ("theta_pos", C.c_float),
                 ("theta_neg", C.c_float), ("label_lo", C.c_int32), ("label_n", C.c_int32),
                 ("n_gen", C.c_int32), ("flags", C.c_uint32)]
+
+
+class kvop_mixed_op(C.Structure):
+    _fields_ = [("op", kvop_op), ("logits_out_dev", C.c_void_p), ("decision_out_dev", C.c_void_p),
+                ("tokens_out_dev", C.c_void_p)]
 
 
 _P = C.c_void_p
@@ -72,6 +78,11 @@ _SIGS = {
     "kvop_proxy_grads": (C.c_int, [_P, _P, _P, _P, C.c_int32, _P, _P, _P]),
     "kvop_proxy_infer": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
     "kvop_proxy_params": (C.c_int, [_P, _P, _P]),
+    "kvop_set_wave_rows": (C.c_int, [C.c_int64]),
+    "kvop_autotune": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.c_int32]),
+    "kvop_tuning_export": (C.c_int32, [_P, C.c_int32]),
+    "kvop_tuning_import": (C.c_int, [C.c_char_p]),
+    "kvop_mixed_eval": (C.c_int, [_P, _P, C.c_int32, C.c_float, _P, _P, _P, _P, _P, C.c_int32, C.c_uint32, _P]),
     "kvop_profile_start": (C.c_int, []),
     "kvop_profile_stop": (C.c_int, [_P, _P, C.c_int32]),
     "kvop_profile_num_classes": (C.c_int32, []),
@@ -282,3 +293,43 @@ def kvop_proxy_infer(proxy, feats_dev, tau: float, cls_dev, conf_dev, answered_d
 
 def kvop_proxy_params(proxy, out_dev, stream=None) -> None:
     _check(lib().kvop_proxy_params(proxy, _dptr(out_dev), _stream(stream)))
+
+
+def kvop_set_wave_rows(rows: int) -> None:
+    _check(lib().kvop_set_wave_rows(int(rows)))
+
+
+def kvop_mixed_eval(pool, ops, r: float, idx_dev, idx_offsets, handles, item_op, item_list, flags: int,
+                    stream=None) -> None:
+    """ops: list of (kvop_op, logits_dev, decision_dev or None, tokens_dev or None)."""
+    arr = (kvop_mixed_op * len(ops))()
+    keep = []
+    for i, (op, lg, dec, tk) in enumerate(ops):
+        arr[i].op = op
+        keep.append(op._keep)
+        arr[i].logits_out_dev = _dptr(lg)
+        arr[i].decision_out_dev = _dptr(dec)
+        arr[i].tokens_out_dev = _dptr(tk)
+    offs, po = _host(idx_offsets, np.int64)
+    h, hp = _host(handles, np.uint64)
+    io, iop = _host(item_op, np.int32)
+    il, ilp = _host(item_list, np.int64)
+    _check(lib().kvop_mixed_eval(pool, C.cast(arr, C.c_void_p), len(ops), float(r), _dptr(idx_dev), po, hp, iop, ilp,
+                                 len(io), int(flags), _stream(stream)))
+
+
+def kvop_autotune(model, rows: int, reps: int = 3, stream=None) -> str:
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().kvop_autotune(model, int(rows), int(reps), _stream(stream), buf, len(buf)))
+    return buf.value.decode()
+
+
+def kvop_tuning_export() -> str:
+    n = int(lib().kvop_tuning_export(None, 0))
+    buf = C.create_string_buffer(n + 1)
+    lib().kvop_tuning_export(buf, n + 1)
+    return buf.value.decode()
+
+
+def kvop_tuning_import(text: str) -> None:
+    _check(lib().kvop_tuning_import(text.encode()))

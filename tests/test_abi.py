@@ -58,3 +58,14 @@ def test_gemm_tile_table_is_named():
         assert n >= 3
         names = [K.kvop_gemm_tile_name(dt, t) for t in range(n)]
         assert len(set(names)) == n and all(names)
+
+
+def test_tuning_table_text_roundtrip():
+    """The tuning table is host state: import/export need no device."""
+    name = K.kvop_gemm_tile_name(K.KVOP_BF16, 1)
+    K.kvop_tuning_import(f"1 2 11264 2048 17 {name}\n")
+    assert f"1 2 11264 2048 17 {name}" in K.kvop_tuning_export()
+    with pytest.raises(K.KvopError):
+        K.kvop_tuning_import("1 2 11264 2048 17 no_such_tile\n")
+    K.kvop_gemm_set_tile(K.KVOP_BF16, 2, 11264, 2048, 131072, 0)     # M=131072 -> bucket 17
+    assert f"1 2 11264 2048 17 {K.kvop_gemm_tile_name(K.KVOP_BF16, 0)}" in K.kvop_tuning_export()
