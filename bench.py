@@ -49,6 +49,8 @@ def main():
                     help="documents the proxy is trained on (labels from the full BF16 r=1 operator)")
     ap.add_argument("--proxy-epochs", type=int, default=20)
     ap.add_argument("--no-proxy", action="store_true")
+    ap.add_argument("--workload", choices=["filter", "mixed"], default="filter",
+                    help="filter: the plain filter at scale (default); mixed: filter/map/join in one pass")
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -63,6 +65,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "mixed":
+        return bench_mixed(args, K, synth, dev)
     shape = synth.SCALE
     t0 = time.time()
     wl = synth.scale_filter(0, n=args.n)
@@ -256,6 +260,128 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(json.dumps(line) + "\n")
+
+
+def bench_mixed(args, K, synth, dev):
+    """Mixed operators (batching form): 16384 documents, lengths lognormal (median 384,
+    sigma 1) in [16, 8192]; one third filter items, one third map items (8 greedy ids over
+    the label slice [256, 512)), one third join-side documents forming 2048 pairs; one
+    32-token suffix per operator; r = 1; BF16 weights/activations and BF16 cache.  The
+    caches exceed HBM, so the items are processed in groups whose documents fit: each
+    group's caches are built (untimed), then its items are evaluated (timed)."""
+    import torch
+    shape = synth.SCALE
+    wl = synth.mixed_batch(0)
+    docs = wl.docs
+    fdocs, mdocs, pairs = wl.extra["filter_docs"], wl.extra["map_docs"], wl.extra["join_pairs"]
+    n_gen, lo, nl = synth.MAP_TOKENS, synth.MAP_SLICE[0], synth.MAP_SLICE[1]
+    w = synth.make_weights(shape, 0)
+    flat = torch.from_numpy(synth.pack_weights(shape, w)).to(dev)
+    del w
+    mb = K.kvop_model_create(K.make_cfg(shape), flat, K.KVOP_BF16)
+    del flat
+    torch.cuda.empty_cache()
+    tiles = autotune(K, mb, [131072, 60000, 5461, 4096], "bf16")
+    opf = K.make_op(K.KVOP_FILTER, wl.suffix, synth.YES_ID, synth.NO_ID)
+    opm = K.make_op(K.KVOP_MAP, wl.extra["suffix_map"], label_lo=lo, label_n=nl, n_gen=n_gen)
+    opj = K.make_op(K.KVOP_JOIN, wl.extra["suffix_join"], synth.YES_ID, synth.NO_ID)
+    probe = K.kvop_pool_create(mb, K.KVOP_KV_BF16, 1 << 20)
+    dbytes = np.array([K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths])
+    K.kvop_pool_destroy(probe)
+    cap = torch.cuda.mem_get_info()[0] - (48 << 30)
+    pool = K.kvop_pool_create(mb, K.KVOP_KV_BF16, cap)
+    G = 1
+    while True:
+        ok = True
+        for g in range(G):
+            need = set(np.array_split(fdocs, G)[g]) | set(np.array_split(mdocs, G)[g]) | \
+                set(np.array_split(pairs, G)[g].ravel().tolist())
+            if dbytes[sorted(need)].sum() > cap - (2 << 30):
+                ok = False
+        if ok:
+            break
+        G += 1
+    log(f"mixed workload: {len(fdocs)} filter, {len(mdocs)} map, {len(pairs)} join items in {G} groups")
+    stream = torch.cuda.current_stream()
+    toks_all = torch.from_numpy(docs.tokens).to(dev)
+    t_mode = {"graph_persistent": 0.0, "eager": 0.0, "separate_calls": 0.0}
+    t_build = 0.0
+    n_items = 0
+    for g in range(G):
+        fg, mg, pg = np.array_split(fdocs, G)[g], np.array_split(mdocs, G)[g], np.array_split(pairs, G)[g]
+        need = sorted(set(fg) | set(mg) | set(pg.ravel().tolist()))
+        sub = docs.subset(need)
+        pos = {dd: i for i, dd in enumerate(need)}
+        torch.cuda.synchronize()
+        t0 = time.time()
+        hsub = K.kvop_kv_build(pool, torch.from_numpy(sub.tokens).to(dev), sub.offsets)
+        torch.cuda.synchronize()
+        t_build += time.time() - t0
+        fidx, foffs = synth.full_lists(sub.lengths)
+        idx = torch.from_numpy(fidx).to(dev)
+        # lists/handles per item: filter docs, map docs, join pairs (two lists each)
+        lists_f = [pos[dd] for dd in fg]
+        lists_m = [pos[dd] for dd in mg]
+        lists_j = [x for a, b in pg for x in (pos[a], pos[b])]
+        all_lists = lists_f + lists_m + lists_j
+        L_off = np.concatenate([[0], np.cumsum(sub.lengths[all_lists])])
+        sel_idx = torch.cat([idx[int(foffs[i]):int(foffs[i + 1])] for i in all_lists])
+        hs = hsub[all_lists]
+        nf, nm, nj = len(lists_f), len(lists_m), len(pg)
+        item_op = np.concatenate([np.zeros(nf), np.ones(nm), 2 * np.ones(nj)]).astype(np.int32)
+        item_list = np.concatenate([np.arange(nf), nf + np.arange(nm), nf + nm + 2 * np.arange(nj)]).astype(np.int64)
+        perm = np.random.default_rng(g).permutation(len(item_op))      # operators interleaved
+        item_op, item_list = item_op[perm], item_list[perm]
+        n_items += nf + nm + nj
+        lf = torch.empty(nf, 2, device=dev)
+        df = torch.empty(nf, dtype=torch.int8, device=dev)
+        lm = torch.empty(nm, n_gen, nl, device=dev)
+        tm = torch.empty(nm, n_gen, dtype=torch.int32, device=dev)
+        lj = torch.empty(nj, 2, device=dev)
+        dj = torch.empty(nj, dtype=torch.int8, device=dev)
+        ops = [(opf, lf, df, None), (opm, lm, None, tm), (opj, lj, dj, None)]
+
+        def timed(fn):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.time()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return max(e0.elapsed_time(e1), (time.time() - t0) * 1e3)
+
+        flags = K.KVOP_MIXED_PERSISTENT | K.KVOP_MIXED_GRAPH
+        K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op, item_list, flags)     # warm-up
+        t_mode["graph_persistent"] += timed(lambda: K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op,
+                                                                      item_list, flags))
+        ref = (lf.cpu().numpy(), tm.cpu().numpy(), lj.cpu().numpy())
+        t_mode["eager"] += timed(lambda: K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op, item_list, 0))
+        same = np.array_equal(ref[0], lf.cpu().numpy()) and np.array_equal(ref[1], tm.cpu().numpy()) and \
+            np.array_equal(ref[2], lj.cpu().numpy())
+
+        def separate():
+            K.kvop_op_eval(pool, opf, 1.0, sel_idx, L_off[:nf + 1], hs[:nf], lf, df)
+            K.kvop_op_eval(pool, opm, 1.0, sel_idx, L_off[nf:nf + nm + 1], hs[nf:nf + nm], lm, None, tm)
+            K.kvop_op_eval(pool, opj, 1.0, sel_idx, L_off[nf + nm:], hs[nf + nm:], lj, dj)
+        t_mode["separate_calls"] += timed(separate)
+        same = same and np.array_equal(ref[0], lf.cpu().numpy()) and np.array_equal(ref[1], tm.cpu().numpy())
+        log(f"group {g}: {len(need)} docs, {nf}/{nm}/{nj} items, graph {t_mode['graph_persistent']:.0f} ms so far, "
+            f"identical results across modes: {same}")
+        K.kvop_kv_release(pool, hsub)
+    K.kvop_pool_destroy(pool)
+    K.kvop_model_destroy(mb)
+    ms = t_mode["graph_persistent"]
+    line = {"metric": "tuples/sec mixed filter/map/join, one pass per wave (batching form)",
+            "value": n_items / (ms / 1e3), "unit": "items/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic",
+            "config": {"workload": "mixed operators: 16384 docs lognormal(median 384, sigma 1) in [16, 8192]; "
+                                   "5462 filter, 5461 map (8 ids over 256 labels), 2048 join pairs; r=1; bf16",
+                       "groups": G, "items": n_items},
+            "modes_items_per_s": {k: n_items / (v / 1e3) for k, v in t_mode.items()},
+            "kv_build_s": t_build, "gemm_tiles": tiles}
+    print(json.dumps(line), flush=True)
 
 
 def autotune(K, model, rows_list, tag):
