@@ -172,7 +172,7 @@ def main():
     fp32 = None
     if not args.no_fp32:
         mf = K.kvop_model_create(cfg, flat, K.KVOP_F32)
-        tune_report += autotune(K, mf, [n * 32, 60000, n], "f32")
+        tune_report.update(autotune(K, mf, [n * 32, 60000, n], "f32"))
         probe = K.kvop_pool_create(mf, K.KVOP_KV_F32, 1 << 20)
         sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
         K.kvop_pool_destroy(probe)

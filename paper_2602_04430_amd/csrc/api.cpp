@@ -128,10 +128,12 @@ struct kvop_model {
   int* dflag = nullptr;   // [0]: list-validation count, [16]: persistent-attention unit counter
   int* hflag = nullptr;
   int n_cu = 0;
+  hipStream_t cap_stream = nullptr;  // graph capture (the legacy null stream cannot be captured)
 
   int qkv_cols() const { return (cfg.n_heads + 2 * cfg.n_kv_heads) * cfg.head_dim; }
   int esz() const { return dt == DT_F32 ? 4 : 2; }
   ~kvop_model() {
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     if (dflag) (void)hipFree(dflag);
     if (hflag) (void)hipHostFree(hflag);
@@ -1291,7 +1293,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     char* ownbuf = (char*)m->ws.p + act;
 
     // ---- the wave's launch sequence (enqueued directly, or captured once and replayed)
-    auto enqueue = [&]() -> kvop_status {
+    auto enqueue = [&](hipStream_t st) -> kvop_status {
       HIPTRY(embed_rows(m->dt, m->embed, (const int32_t*)(md + o_tok), (int)rows, d, c.vocab, bufs.x, st));
       LayerPlan lp{};
       lp.rows = (int)rows;
@@ -1394,26 +1396,43 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     // replay one captured graph when asked to
     const bool graph_wave = use_graph && full && w > 0;
     if (!graph_wave) {
-      kvop_status s = enqueue();
+      kvop_status s = enqueue(st);
       if (s != KVOP_OK) { cleanup_graph(); return s; }
       if (full) full_meta = mir.size;
       continue;
     }
     if (!gexec) {
+      // capture on the library's own stream (capturing records, it does not execute), then
+      // launch the instantiated graph on the caller's stream
       if (mir.size != full_meta) { cleanup_graph(); return fail(KVOP_EDEVICE, "wave layout changed"); }
+      if (!m->cap_stream && hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        m->cap_stream = nullptr;
+        return fail(KVOP_EDEVICE, "capture stream creation failed");
+      }
       g_prof.capturing = true;
-      hipError_t ce = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
-      kvop_status s = ce == hipSuccess ? enqueue() : fail(KVOP_EDEVICE, "hipStreamBeginCapture failed");
-      hipError_t ee = hipStreamEndCapture(st, &graph);
+      hipError_t ce = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
+      kvop_status s = KVOP_OK;
+      hipError_t ee = hipSuccess;
+      if (ce == hipSuccess) {
+        s = enqueue(m->cap_stream);
+        ee = hipStreamEndCapture(m->cap_stream, &graph);
+      }
       g_prof.capturing = false;
-      if (s != KVOP_OK) { cleanup_graph(); return s; }
-      if (ee != hipSuccess) { cleanup_graph(); return fail(KVOP_EDEVICE, "hipStreamEndCapture failed"); }
+      if (ce != hipSuccess || s != KVOP_OK || ee != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup_graph();
+        if (s != KVOP_OK) return s;
+        return fail(KVOP_EDEVICE, ce != hipSuccess ? "hipStreamBeginCapture failed" : "hipStreamEndCapture failed");
+      }
       if (hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
         cleanup_graph();
         return fail(KVOP_EDEVICE, "hipGraphInstantiate failed");
       }
     }
     if (hipGraphLaunch(gexec, st) != hipSuccess) {
+      (void)hipGetLastError();
       cleanup_graph();
       return fail(KVOP_EDEVICE, "hipGraphLaunch failed");
     }
