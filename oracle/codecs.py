@@ -7,6 +7,7 @@
   values beyond 448 to +-448.
 * Block quantisation of the KV cache: one FP32 scale per block (amax / 448, or 1 when the
   block is all zero); codes are the E4M3 encoding of x / scale; decoding is code * scale.
+  A cache block is 16 consecutive rows of one (layer, kv head, K or V) array.
 
 Written from the format definitions; pinned against library casts in the tests.
 """
@@ -80,3 +81,19 @@ def quantize_block(block: np.ndarray):
     sc = block_scale(block)
     q = (np.asarray(block, np.float32) / sc).astype(np.float32)
     return e4m3_encode(q), sc
+
+
+CACHE_BLOCK_ROWS = 16
+
+
+def fp8_cache_roundtrip(a: np.ndarray) -> np.ndarray:
+    """What an FP8-E4M3 cache holds for one layer's keys or values a [Hkv, L, D]: each block
+    of 16 rows of one head is quantised on its own (quantize_block) and decoded as
+    code * scale.  Returned in float64."""
+    a = np.asarray(a, np.float64)
+    out = np.empty_like(a)
+    for h in range(a.shape[0]):
+        for r0 in range(0, a.shape[1], CACHE_BLOCK_ROWS):
+            codes, sc = quantize_block(a[h, r0:r0 + CACHE_BLOCK_ROWS])
+            out[h, r0:r0 + CACHE_BLOCK_ROWS] = e4m3_decode(codes) * np.float64(sc)
+    return out

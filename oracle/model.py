@@ -116,8 +116,10 @@ class Model:
         return self.w[f"L{i}.{name}"]
 
     # one decoder layer over new rows x [n, d] at positions pos, with prior context keys
-    # ctxK/ctxV [Hkv, m, D] (already rotated) and visibility [n, m + n] over (context, new rows)
-    def layer(self, i, x, pos, ctxK, ctxV, visible):
+    # ctxK/ctxV [Hkv, m, D] (already rotated) and visibility [n, m + n] over (context, new rows).
+    # store, when given, maps the new rows' keys/values [Hkv, n, D] to what a cache of that
+    # number format holds; the attention then reads the stored values, and they are returned.
+    def layer(self, i, x, pos, ctxK, ctxV, visible, store=None):
         s = self.s
         n = x.shape[0]
         h = rmsnorm(x, self.L(i, "attn_norm"), s.rms_eps)
@@ -126,6 +128,8 @@ class Model:
         v = (h @ self.L(i, "wv").T).reshape(n, s.n_kv_heads, s.head_dim).transpose(1, 0, 2)
         q = rope(q, pos, s.rope_theta)
         k = rope(k, pos, s.rope_theta)
+        if store is not None:
+            k, v = store(k), store(v)
         K = np.concatenate([ctxK, k], axis=1)
         V = np.concatenate([ctxV, v], axis=1)
         a = attention(q, K, V, visible)
@@ -159,9 +163,14 @@ class Cache:
         return self.K.shape[2]
 
 
-def kv_build(m: Model, tokens: Sequence[int]) -> Cache:
+def kv_build(m: Model, tokens: Sequence[int], store=None) -> Cache:
     """Prefill one document causally at positions 0..L-1 and keep every layer's K and V
-    (Section 5, "Offline: KV Cache Creation")."""
+    (Section 5, "Offline: KV Cache Creation").
+
+    store (optional) is the cache's number format as a round trip [Hkv, L, D] -> same
+    shape (e.g. FP8 blocks, codecs.fp8_cache_roundtrip): every layer keeps the stored
+    values, and the document's own causal attention already reads them, as it does when
+    the prefill attends over the cache it is writing."""
     toks = np.asarray(tokens)
     L = len(toks)
     x = m.w["embed"][toks]
@@ -169,7 +178,7 @@ def kv_build(m: Model, tokens: Sequence[int]) -> Cache:
     causal = np.tril(np.ones((L, L), bool))
     Ks, Vs = [], []
     for i in range(m.s.n_layers):
-        x, k, v = m.layer(i, x, pos, m.empty_ctx(), m.empty_ctx(), causal)
+        x, k, v = m.layer(i, x, pos, m.empty_ctx(), m.empty_ctx(), causal, store)
         Ks.append(k)
         Vs.append(v)
     pooled = m.final(x).mean(axis=0)

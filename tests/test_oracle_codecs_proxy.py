@@ -67,6 +67,38 @@ def test_block_quantisation_roundtrip_error_bound():
     assert s0 == 1.0 and np.all(z == 0)
 
 
+def test_fp8_cache_roundtrip_blocks_by_brute_force():
+    """Each 16-row block of each head (and the ragged last block) is scaled by its own amax
+    and every element goes to the nearest of the 256 E4M3 values (exhaustive search)."""
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((3, 37, 8)) * np.array([0.1, 3.0, 40.0])[:, None, None]
+    a[1, 20] *= 50.0                                   # one block with a large outlier
+    got = codecs.fp8_cache_roundtrip(a)
+    table = codecs.e4m3_decode_table()
+    finite = table[np.isfinite(table)]
+    for h in range(3):
+        for r0 in (0, 16, 32):
+            blk = a[h, r0:r0 + 16]
+            sc = np.float64(np.float32(np.float32(np.abs(blk).max()) / np.float32(448.0)))
+            q = (blk.astype(np.float32) / np.float32(sc)).astype(np.float64)
+            near = finite[np.argmin(np.abs(q[..., None] - finite), axis=-1)]
+            np.testing.assert_array_equal(got[h, r0:r0 + 16], near * sc)
+    # blocks and heads are independent: changing block 2 of head 0 changes nothing else
+    b = a.copy()
+    b[0, 33] *= 7.0
+    diff = codecs.fp8_cache_roundtrip(b) != got
+    assert diff[0, 32:].any() and not diff[0, :32].any() and not diff[1:].any()
+
+
+def test_fp8_cache_roundtrip_exact_on_representable_blocks():
+    rng = np.random.default_rng(6)
+    table = codecs.e4m3_decode_table()
+    codes = rng.integers(0, 0x7E, (2, 32, 8))
+    codes[:, ::16, 0] = 0x7E                            # 448 in every block: scale = 2^-5 exactly
+    a = table[codes] * rng.choice([-1.0, 1.0], codes.shape) * 2.0 ** -5
+    np.testing.assert_array_equal(codecs.fp8_cache_roundtrip(a), a)
+
+
 # ----------------------------------------------------------------------------- proxy
 
 def _params(rng, d_in=12, d_h=7, n_out=2, scale=0.5):

@@ -346,3 +346,39 @@ def test_oracle_reproduces_stored_tiny_filter_values():
     got = np.array(tiny_filter_rows(), np.float64)
     np.testing.assert_array_equal(got[:, 0], ref[:, 0])
     np.testing.assert_allclose(got[:, 1:], ref[:, 1:], rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------- cache number formats
+
+def test_kv_build_store_hook_identity_and_zero():
+    """With an identity format the cache is unchanged; with a format that stores zeros the
+    prefill's own attention reads those zeros, so every layer's attention adds nothing:
+    the result equals a model whose output projections are zero."""
+    m = micro_model(seed=4)
+    doc = _doc(m, 21, 13)
+    plain = om.kv_build(m, doc)
+    ident = om.kv_build(m, doc, store=lambda a: a)
+    np.testing.assert_array_equal(ident.K, plain.K)
+    np.testing.assert_array_equal(ident.pooled, plain.pooled)
+    zero = om.kv_build(m, doc, store=np.zeros_like)
+    w0 = dict(m.w)
+    for i in range(m.s.n_layers):
+        w0[f"L{i}.wo"] = np.zeros_like(m.w[f"L{i}.wo"])
+    no_attn = om.kv_build(om.Model(MICRO, w0), doc)
+    np.testing.assert_array_equal(zero.pooled, no_attn.pooled)
+    assert np.all(zero.K == 0) and np.all(zero.V == 0)
+
+
+def test_fp8_format_cache_stays_close_and_is_what_later_layers_see():
+    """The FP8 format moves the cache by at most the format's rounding in layer 0 (its
+    input does not depend on the cache), and later layers differ from the unquantised
+    cache by more than their own rounding because their inputs already saw FP8 values."""
+    from oracle import codecs
+    m = micro_model(seed=5)
+    doc = _doc(m, 40, 14)
+    plain = om.kv_build(m, doc)
+    q = om.kv_build(m, doc, store=codecs.fp8_cache_roundtrip)
+    np.testing.assert_array_equal(q.K[0], codecs.fp8_cache_roundtrip(plain.K[0]))
+    np.testing.assert_array_equal(q.V[0], codecs.fp8_cache_roundtrip(plain.V[0]))
+    assert not np.array_equal(q.K[1], codecs.fp8_cache_roundtrip(plain.K[1]))
+    assert rel_err(q.K, plain.K) < 0.1
