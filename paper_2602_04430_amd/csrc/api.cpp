@@ -231,9 +231,15 @@ struct LayerBufs {
   void* act;
 };
 
-// Plan of one decoder layer over `rows` activation rows.  Only the rows
-// r*sel_stride + sel_off (r < n_sel) continue past the attention (the K/V of every row are
-// still produced): the last layer of op_eval continues with the last suffix row only.
+// Rows that continue past the attention: r*stride + off for r < n.
+struct SelGroup {
+  int n, stride, off;
+};
+constexpr int kMaxSelGroups = 8;
+
+// Plan of one decoder layer over `rows` activation rows.  Only the rows of the selection
+// groups continue past the attention (the K/V of every row are still produced): the last
+// layer of op_eval continues with the last suffix row of each item only.
 struct LayerPlan {
   int rows;
   const int32_t* pos;
@@ -243,7 +249,10 @@ struct LayerPlan {
   const void* own;           // otherwise: explicit own buffer
   int64_t own_stride;
   int own_kcol, own_vcol;
-  int n_sel, sel_stride, sel_off;  // rows continuing after attention (n_sel == rows: all)
+  int n_groups;                    // selection groups (all rows: one group {rows, 1, 0})
+  SelGroup sel[kMaxSelGroups];
+  void select_all() { n_groups = 1; sel[0] = SelGroup{rows, 1, 0}; }
+  void select_one(int n, int stride, int off) { n_groups = 1; sel[0] = SelGroup{n, stride, off}; }
 };
 
 // skip_tail: stop once this layer's keys/values exist (prefill's last layer when the final
@@ -302,11 +311,13 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
     if (a.counter) HIPTRY(fill_i32(a.counter, 0, 1, st));
     HIPTRY(attention(dt, kvdt, D, a, st));
   }
-  // rows continuing: all, or a strided selection (last row of each item)
-  const int n = lp.n_sel;
-  const int64_t sa = (int64_t)lp.sel_stride;
-  const char* attn_sel = (const char*)b.attn + (int64_t)lp.sel_off * H * D * m->esz();
-  float* x_sel = b.x + (int64_t)lp.sel_off * d;
+  // rows continuing: all, or strided selections (last row of each item)
+  for (int gi = 0; gi < lp.n_groups; gi++) {
+  const int n = lp.sel[gi].n;
+  if (n <= 0) continue;
+  const int64_t sa = (int64_t)lp.sel[gi].stride;
+  const char* attn_sel = (const char*)b.attn + (int64_t)lp.sel[gi].off * H * D * m->esz();
+  float* x_sel = b.x + (int64_t)lp.sel[gi].off * d;
   {
     ProfScope ps(PC_GEMM_O, st);
     GemmShape s{n, d, H * D, sa * H * D, H * D, sa * d};
@@ -322,6 +333,7 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
     ProfScope ps(PC_GEMM_DOWN, st);
     GemmShape s{n, d, F, F, F, sa * d};
     HIPTRY(gemm(dt, DT_F32, EPI_ADD, gemm_pick_tile(dt, EPI_ADD, s), b.act, W.wdown, x_sel, s, st));
+  }
   }
   return KVOP_OK;
 }
@@ -653,9 +665,7 @@ kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* of
     lp.attn.Pmax = Pmax;
     lp.own_from_qkv = false;
     lp.own = nullptr;
-    lp.n_sel = (int)rows;
-    lp.sel_stride = 1;
-    lp.sel_off = 0;
+    lp.select_all();
     for (int l = 0; l < c.n_layers; l++) {
       bool tail = (l + 1 < c.n_layers) || pooled != nullptr;
       kvop_status s = run_layer(m, l, b, lp, p->base, p->kvdt, (const KvBlock*)(md + o_blk), (int)blocks.size(), st,
@@ -912,15 +922,8 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     lp.own_from_qkv = true;
     for (int l = 0; l < c.n_layers; l++) {
       const bool last = l + 1 == c.n_layers;
-      if (last) {  // only the last suffix row of every item feeds the head
-        lp.n_sel = B;
-        lp.sel_stride = S;
-        lp.sel_off = S - 1;
-      } else {
-        lp.n_sel = (int)rows;
-        lp.sel_stride = 1;
-        lp.sel_off = 0;
-      }
+      if (last) lp.select_one(B, S, S - 1);  // only the last suffix row of every item feeds the head
+      else lp.select_all();
       kvop_status s = run_layer(m, l, bufs, lp, p->base, p->kvdt, nullptr, 0, st);
       if (s != KVOP_OK) return s;
       if (kind == KVOP_MAP) {
@@ -976,9 +979,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
       dp.own_stride = own_ld;
       dp.own_kcol = 0;
       dp.own_vcol = Hkv * D;
-      dp.n_sel = B;
-      dp.sel_stride = 1;
-      dp.sel_off = 0;
+      dp.select_all();
       for (int l = 0; l < c.n_layers; l++) {
         char* own_l = ownbuf + (size_t)l * B * rows_per_item * own_ld * e;
         dp.own = own_l;
@@ -1306,10 +1307,18 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
       lp.attn.counter = persistent ? counter : nullptr;
       lp.attn.persistent_wgs = 2 * m->n_cu;
       lp.own_from_qkv = true;
-      lp.n_sel = (int)rows;  // every row continues (operators read different last rows)
-      lp.sel_stride = 1;
-      lp.sel_off = 0;
       for (int l = 0; l < c.n_layers; l++) {
+        // the last layer continues with each operator's last suffix rows only (one strided
+        // group per operator); with more operators than groups every row continues
+        lp.select_all();
+        if (l + 1 == c.n_layers && n_ops <= kMaxSelGroups) {
+          lp.n_groups = 0;
+          for (int k = 0; k < n_ops; k++) {
+            if (blk_n[k] == 0) continue;
+            const int S = ops[k].op.suffix_len;
+            lp.sel[lp.n_groups++] = SelGroup{blk_n[k], S, blk_row[k] + S - 1};
+          }
+        }
         kvop_status s = run_layer(m, l, bufs, lp, p->base, p->kvdt, nullptr, 0, st);
         if (s != KVOP_OK) return s;
         if (nm > 0)
