@@ -44,7 +44,12 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="documents (the workload has 4096)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 path")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-cache variant")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="documents the oracle is timed on")
+    ap.add_argument("--cpu-sample", type=int, default=4, help="documents the oracle is timed on (0: skip)")
+    ap.add_argument("--tuning", default=None,
+                    help="import this GEMM tuning table instead of running the autotuner (profiling runs)")
+    ap.add_argument("--export-tuning", default=None, help="write the GEMM tuning table used to this file")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with plain 1 GiB device copies (calibration of HBM byte counters)")
     ap.add_argument("--proxy-train", type=int, default=16384,
                     help="documents the proxy is trained on (labels from the full BF16 r=1 operator)")
     ap.add_argument("--proxy-epochs", type=int, default=20)
@@ -119,7 +124,12 @@ def main():
     result = {}
     # ------------------------------------------------------------------ BF16 path
     mb = K.kvop_model_create(cfg, flat, K.KVOP_BF16)
-    tune_report = autotune(K, mb, [n * 32, 60000, n], "bf16")
+    if args.tuning:
+        with open(args.tuning) as f:
+            K.kvop_tuning_import(f.read())
+        tune_report = {"imported": args.tuning}
+    else:
+        tune_report = autotune(K, mb, [n * 32, 60000, n], "bf16")
     proxy = None
     if not args.no_proxy:
         proxy, proxy_info = train_proxy(K, synth, mb, shape, wl.suffix, args, dev)
@@ -172,7 +182,8 @@ def main():
     fp32 = None
     if not args.no_fp32:
         mf = K.kvop_model_create(cfg, flat, K.KVOP_F32)
-        tune_report.update(autotune(K, mf, [n * 32, 60000, n], "f32"))
+        if not args.tuning:
+            tune_report.update(autotune(K, mf, [n * 32, 60000, n], "f32"))
         probe = K.kvop_pool_create(mf, K.KVOP_KV_F32, 1 << 20)
         sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
         K.kvop_pool_destroy(probe)
@@ -204,8 +215,10 @@ def main():
     torch.cuda.empty_cache()
 
     # ------------------------------------------------------------------ CPU baseline: the oracle
-    cpu = oracle_baseline(shape, w, docs, wl.suffix, args.cpu_sample, bf16_out[1.0][0],
-                          None if fp32 is None else fp32["logits"])
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = oracle_baseline(shape, w, docs, wl.suffix, args.cpu_sample, bf16_out[1.0][0],
+                              None if fp32 is None else fp32["logits"])
 
     # ------------------------------------------------------------------ roofline of the dominant kernel
     gu_ms, gu_cnt = prof["gemm_gate_up"]
@@ -257,6 +270,11 @@ def main():
                               "bf16_vs_fp32_max_abs_logit_diff": float(np.max(np.abs(bf16_out[1.0][0] - fp32["logits"]))),
                               "speedup_bf16_over_fp32": value / fp32["tuples_per_s"]}
     print(json.dumps(line), flush=True)
+    if args.export_tuning:
+        with open(args.export_tuning, "w") as f:
+            f.write(K.kvop_tuning_export())
+    if args.copy_probe:
+        copy_probe(dev)
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(json.dumps(line) + "\n")
@@ -574,7 +592,19 @@ def time_cascade(K, px, info, pool, handles, pooled, lists, op, full_out, n, arg
     return out
 
 
-def oracle_baseline(shape, w, docs, suffix, n_sample, gpu_bf16_logits, gpu_f32_logits):
+def copy_probe(dev):
+    """Three plain device-to-device copies of 1 GiB: each reads and writes exactly 2^30 bytes,
+    which calibrates the HBM byte counters (FETCH_SIZE, WRITE_SIZE) against known traffic."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy probe: 3 x 1 GiB device copies done")
+
+
+def oracle_baseline(shape, w, docs, suffix, n_sample, gpu_bf16_logits, gpu_f32_logits, min_seconds=10.0):
     """Time the FP64 oracle's filter evaluation (the suffix over cached rows) on the first
     n_sample documents, after building their caches with the oracle (not timed)."""
     from oracle import model as om
@@ -591,16 +621,22 @@ def oracle_baseline(shape, w, docs, suffix, n_sample, gpu_bf16_logits, gpu_f32_l
         caches.append(om.kv_build(m, docs.doc(i)))
         log(f"oracle kv_build doc {i} (L={docs.lengths[i]}) done at {time.time() - t0:.1f} s")
     t_build = time.time() - t0
+    # evaluate the sampled tuples in passes until at least min_seconds of CPU work is timed
     t1 = time.time()
-    res = []
-    for i in range(n_sample):
-        res.append(om.filter_eval(m, caches[i], np.arange(docs.lengths[i]), suffix, synth.YES_ID, synth.NO_ID))
+    evals = 0
+    while True:
+        res = []
+        for i in range(n_sample):
+            res.append(om.filter_eval(m, caches[i], np.arange(docs.lengths[i]), suffix, synth.YES_ID, synth.NO_ID))
+        evals += n_sample
+        if time.time() - t1 >= min_seconds:
+            break
     t_eval = time.time() - t1
     ref = np.stack([r.logits for r in res])
-    out = {"value": n_sample / t_eval, "unit": "tuples/s", "cores": int(threads), "kind": "oracle",
+    out = {"value": evals / t_eval, "unit": "tuples/s", "cores": int(threads), "kind": "oracle",
            "sample": f"FP64 NumPy oracle filter evaluation (r=1) of the first {n_sample} of the 4096 documents "
-                     f"(L={[int(x) for x in docs.lengths[:n_sample]]}), caches built by the oracle beforehand "
-                     f"({t_build:.1f} s, not in the rate)",
+                     f"(L={[int(x) for x in docs.lengths[:n_sample]]}), {evals // n_sample} passes, {evals} "
+                     f"evaluations; caches built by the oracle beforehand ({t_build:.1f} s, not in the rate)",
            "seconds": t_eval,
            "bf16_max_abs_logit_err_vs_oracle": float(np.max(np.abs(gpu_bf16_logits[:n_sample] - ref)))}
     if gpu_f32_logits is not None:

@@ -272,7 +272,8 @@ kvop_status kvop_autotune(kvop_model* model, int64_t rows, int32_t reps, void* s
 /* The tuning table as text lines "dtype epilogue N K mbucket tile_name"; returns the full
  * length (write at most len-1 bytes + terminator into buf, which may be NULL). */
 int32_t kvop_tuning_export(char* buf, int32_t len);
-/* Load lines in the export format into the tuning table (EINVAL if a line is not understood). */
+/* Load lines in the export format into the tuning table; empty lines and lines starting
+ * with '#' are skipped (EINVAL if another line is not understood). */
 kvop_status kvop_tuning_import(const char* text);
 /* Record the best tile for (dtype, epilogue, N, K, M) in the library's tuning table
  * (used by later kvop_kv_build / kvop_op_eval calls). */

@@ -1538,7 +1538,7 @@ kvop_status kvop_tuning_import(const char* text) {
     size_t nl = s.find('\n', pos);
     std::string line = s.substr(pos, nl == std::string::npos ? std::string::npos : nl - pos);
     pos = nl == std::string::npos ? s.size() : nl + 1;
-    if (line.empty()) continue;
+    if (line.empty() || line[0] == '#') continue;
     int dt, epi, N, K, mb;
     char name[128];
     if (sscanf(line.c_str(), "%d %d %d %d %d %127s", &dt, &epi, &N, &K, &mb, name) != 6 ||
