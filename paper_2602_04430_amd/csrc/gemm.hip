@@ -1,7 +1,9 @@
 // Dense projections of the decoder on MFMA: C = A B^T, both operands K-contiguous.
 //
-// Work split: one workgroup of 4 wavefronts per BM x BN output tile; each wavefront owns
-// a WM x WN sub-tile built from 16x16 MFMA blocks.  K advances in BK slabs staged in LDS
+// Work split: one workgroup of NW (4 or 8) wavefronts per BM x BN output tile; each
+// wavefront owns a WM x WN sub-tile built from 16x16 MFMA blocks.  Larger wavefront tiles
+// read fewer LDS bytes per MFMA ((WM + WN) / (WM * WN) bytes per flop); eight wavefronts
+// put two on every SIMD, so one's LDS reads overlap the other's MFMAs.  K advances in BK slabs staged in LDS
 // (two buffers): the next slab is fetched from global memory into registers while the
 // current one feeds the MFMAs, then written to the other buffer, one barrier per slab.
 // FP32 uses v_mfma_f32_16x16x4f32 (four MFMAs per 16-byte LDS read); BF16 uses the
@@ -23,15 +25,16 @@ namespace kvop {
 //   0: padded rows (BK + one chunk) — chunk c of row r at r*LDK + c*VEC
 //   1: unpadded, chunk c of row r stored at slot c ^ ((r >> 1) & (CPR-1))
 //   2: unpadded, chunk c of row r stored at slot c ^ (r & (CPR-1))
-template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
+template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
                                                       int64_t ldb, int64_t ldc, int tiles_m) {
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   constexpr int LDK = BK + (SWZ == 0 ? VEC : 0);  // LDS row pitch (elements)
   constexpr int CPR = BK / VEC;             // chunks per tile row
-  constexpr int ACH = BM * CPR / 256;
-  constexpr int BCH = BN * CPR / 256;
+  constexpr int NT = 64 * NW;               // threads
+  constexpr int ACH = BM * CPR / NT;
+  constexpr int BCH = BN * CPR / NT;
   constexpr int MI = WM / 16, NI = WN / 16;
   constexpr int WN_CNT = BN / WN;
   constexpr int KSUB = 4 * VEC;             // K consumed per MFMA step group
@@ -40,8 +43,8 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
     else if constexpr (SWZ == 2) return c ^ (r & (CPR - 1));
     else return c;
   };
-  static_assert((BM / WM) * (BN / WN) == 4, "4 wavefronts");
-  static_assert(ACH * 256 == BM * CPR && BCH * 256 == BN * CPR, "tile/thread mismatch");
+  static_assert((BM / WM) * (BN / WN) == NW, "one wavefront per sub-tile");
+  static_assert(ACH * NT == BM * CPR && BCH * NT == BN * CPR, "tile/thread mismatch");
   static_assert(EPI != EPI_SWIGLU || (NI % 2 == 0), "swiglu needs gate/up block pairs");
 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -69,13 +72,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
   auto gload = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < ACH; i++) {
-      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
+      int c = tid + i * NT, r = c / CPR, kc = (c % CPR) * VEC;
       int gm = m0 + r, gk = k0 + kc;
       ra[i] = (gm < M && gk < K) ? *reinterpret_cast<const u32x4*>(A + (int64_t)gm * lda + gk) : u32x4{0, 0, 0, 0};
     }
 #pragma unroll
     for (int i = 0; i < BCH; i++) {
-      int c = tid + i * 256, r = c / CPR, kc = (c % CPR) * VEC;
+      int c = tid + i * NT, r = c / CPR, kc = (c % CPR) * VEC;
       int gn = n0 + r, gk = k0 + kc;
       rb[i] = (gn < N && gk < K) ? *reinterpret_cast<const u32x4*>(B + (int64_t)gn * ldb + gk) : u32x4{0, 0, 0, 0};
     }
@@ -85,12 +88,12 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
     T* Bs = As + BM * LDK;
 #pragma unroll
     for (int i = 0; i < ACH; i++) {
-      int c = tid + i * 256, r = c / CPR;
+      int c = tid + i * NT, r = c / CPR;
       *reinterpret_cast<u32x4*>(As + r * LDK + slot(r, c % CPR) * VEC) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < BCH; i++) {
-      int c = tid + i * 256, r = c / CPR;
+      int c = tid + i * NT, r = c / CPR;
       *reinterpret_cast<u32x4*>(Bs + r * LDK + slot(r, c % CPR) * VEC) = rb[i];
     }
   };
@@ -184,29 +187,35 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const T* __restrict__ A, c
 
 // ------------------------------------------------------------------ tile table
 struct TileCfg {
-  int BM, BN, BK, WM, WN, SWZ;
+  int BM, BN, BK, WM, WN, SWZ, NW;
   const char* name;
 };
 static const TileCfg kF32Tiles[] = {
-    {128, 128, 32, 64, 64, 0, "f32_128x128x32_w64x64"},
-    {64, 128, 32, 32, 64, 0, "f32_64x128x32_w32x64"},
-    {128, 64, 32, 64, 32, 0, "f32_128x64x32_w64x32"},
-    {128, 128, 32, 64, 64, 1, "f32_128x128x32_w64x64_swz1"},
+    {128, 128, 32, 64, 64, 0, 4, "f32_128x128x32_w64x64"},
+    {64, 128, 32, 32, 64, 0, 4, "f32_64x128x32_w32x64"},
+    {128, 64, 32, 64, 32, 0, 4, "f32_128x64x32_w64x32"},
+    {128, 128, 32, 64, 64, 1, 4, "f32_128x128x32_w64x64_swz1"},
 };
 static const TileCfg kBf16Tiles[] = {
-    {128, 128, 64, 64, 64, 0, "bf16_128x128x64_w64x64"},
-    {256, 128, 64, 128, 64, 0, "bf16_256x128x64_w128x64"},
-    {128, 256, 64, 64, 128, 0, "bf16_128x256x64_w64x128"},
-    {64, 128, 64, 32, 64, 0, "bf16_64x128x64_w32x64"},
-    {256, 256, 64, 128, 128, 0, "bf16_256x256x64_w128x128"},
-    {256, 256, 32, 128, 128, 0, "bf16_256x256x32_w128x128"},
-    {128, 128, 64, 64, 64, 1, "bf16_128x128x64_w64x64_swz1"},
-    {128, 128, 64, 64, 64, 2, "bf16_128x128x64_w64x64_swz2"},
-    {256, 256, 64, 128, 128, 1, "bf16_256x256x64_w128x128_swz1"},
-    {256, 128, 64, 128, 64, 1, "bf16_256x128x64_w128x64_swz1"},
+    {128, 128, 64, 64, 64, 0, 4, "bf16_128x128x64_w64x64"},
+    {256, 128, 64, 128, 64, 0, 4, "bf16_256x128x64_w128x64"},
+    {128, 256, 64, 64, 128, 0, 4, "bf16_128x256x64_w64x128"},
+    {64, 128, 64, 32, 64, 0, 4, "bf16_64x128x64_w32x64"},
+    {256, 256, 64, 128, 128, 0, 4, "bf16_256x256x64_w128x128"},
+    {256, 256, 32, 128, 128, 0, 4, "bf16_256x256x32_w128x128"},
+    {128, 128, 64, 64, 64, 1, 4, "bf16_128x128x64_w64x64_swz1"},
+    {128, 128, 64, 64, 64, 2, 4, "bf16_128x128x64_w64x64_swz2"},
+    {256, 256, 64, 128, 128, 1, 4, "bf16_256x256x64_w128x128_swz1"},
+    {256, 128, 64, 128, 64, 1, 4, "bf16_256x128x64_w128x64_swz1"},
+    {256, 256, 64, 128, 64, 1, 8, "bf16_256x256x64_8w_w128x64_swz1"},
+    {256, 256, 64, 64, 128, 1, 8, "bf16_256x256x64_8w_w64x128_swz1"},
+    {256, 256, 64, 128, 64, 2, 8, "bf16_256x256x64_8w_w128x64_swz2"},
+    {256, 256, 64, 128, 64, 0, 8, "bf16_256x256x64_8w_w128x64"},
+    {256, 128, 64, 64, 64, 1, 8, "bf16_256x128x64_8w_w64x64_swz1"},
+    {128, 256, 64, 64, 64, 1, 8, "bf16_128x256x64_8w_w64x64_swz1"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 10; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 16; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -220,18 +229,18 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
   return true;
 }
 
-template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ>
+template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
   size_t lds = 2 * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ>;
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(256), lds, st, (const T*)A, (const T*)B, C, s.M, s.N, s.K,
+  hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(64 * NW), lds, st, (const T*)A, (const T*)B, C, s.M, s.N, s.K,
                      s.lda, s.ldb, s.ldc, tiles_m);
   return hipGetLastError();
 }
@@ -256,7 +265,13 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 6: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 1>(A, B, C, s, st);
       case 7: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 2>(A, B, C, s, st);
       case 8: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 1>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 1>(A, B, C, s, st);
+      case 9: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 1>(A, B, C, s, st);
+      case 10: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8>(A, B, C, s, st);
+      case 11: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8>(A, B, C, s, st);
+      case 12: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 2, 8>(A, B, C, s, st);
+      case 13: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 0, 8>(A, B, C, s, st);
+      case 14: return launch_t<T, TO, EPI, 256, 128, 64, 64, 64, 1, 8>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 128, 256, 64, 64, 64, 1, 8>(A, B, C, s, st);
     }
   }
 }
