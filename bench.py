@@ -312,7 +312,6 @@ def bench_mixed(args, K, synth, dev):
     mb = K.kvop_model_create(K.make_cfg(shape), flat, K.KVOP_BF16)
     del flat
     torch.cuda.empty_cache()
-    tiles = autotune(K, mb, [131072, 60000, 5461, 4096], "bf16")
     opf = K.make_op(K.KVOP_FILTER, wl.suffix, synth.YES_ID, synth.NO_ID)
     opm = K.make_op(K.KVOP_MAP, wl.extra["suffix_map"], label_lo=lo, label_n=nl, n_gen=n_gen)
     opj = K.make_op(K.KVOP_JOIN, wl.extra["suffix_join"], synth.YES_ID, synth.NO_ID)
@@ -333,6 +332,12 @@ def bench_mixed(args, K, synth, dev):
             break
         G += 1
     log(f"mixed workload: {len(fdocs)} filter, {len(mdocs)} map, {len(pairs)} join items in {G} groups")
+    # tune the projections at the row counts the waves run: full waves, and the per-operator
+    # last-layer rows and decode rows
+    sizes = [len(np.array_split(x, G)[0]) for x in (fdocs, mdocs, pairs)]
+    n_waves = -(-32 * sum(sizes) // WAVE_ROWS)
+    per = [-(-x // n_waves) for x in sizes]
+    tiles = autotune(K, mb, sorted({32 * sum(per), per[0], per[2]}), "bf16")
     stream = torch.cuda.current_stream()
     modes = {"graph_persistent": K.KVOP_MIXED_PERSISTENT | K.KVOP_MIXED_GRAPH,
              "persistent": K.KVOP_MIXED_PERSISTENT, "eager": 0}

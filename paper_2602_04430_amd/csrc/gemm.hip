@@ -144,44 +144,69 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
     buf ^= 1;
   }
 
-  // epilogue: lane holds C[row0 + 4*(lane/16) + r][col0 + lane%16]
-  const int rbase = m0 + wm * WM + (lane >> 4) * 4;
-  const int cbase = n0 + wn * WN + (lane & 15);
-  if constexpr (EPI == EPI_SWIGLU) {
-    TO* C = reinterpret_cast<TO*>(Cv);
-    // column block (n0 + wn*WN)/16 + j: even = gate, odd = up of the same 16 features
+  // ---- epilogue.  Lane holds C[row0 + 4*(lane/16) + r][col0 + 16*j + lane%16].  Output
+  // columns of one 16-row slab are first formed in registers (SwiGLU pairs gate block j with
+  // up block j+1), staged row-major through this wavefront's slice of LDS (free after the
+  // last barrier), then written with 16-byte row-contiguous accesses (FP32 residual add:
+  // 16-byte read-modify-write).  A ragged column edge or an unaligned C uses scalar accesses.
+  constexpr int OW = EPI == EPI_SWIGLU ? WN / 2 : WN;       // output columns per wavefront
+  constexpr int OJ = OW / 16;                               // 16-column output blocks
+  constexpr int EP = OW + 4;                                // LDS slab pitch (floats)
+  constexpr bool OUT_BF16 = sizeof(TO) == 2;
+  constexpr int VW = OUT_BF16 ? 8 : 4;                      // output elements per 16-byte access
+  constexpr int LPR = OW / VW;                              // lanes per row
+  constexpr int RPP = 64 / LPR;                             // rows per pass
+  static_assert(64 % LPR == 0 && 16 % RPP == 0, "epilogue lane split");
+  static_assert(NW * 16 * EP * 4 <= 2 * (BM + BN) * LDK * (int)sizeof(T), "epilogue staging fits the slab buffers");
+  const int n_out = EPI == EPI_SWIGLU ? N / 2 : N;
+  const int col0 = (EPI == EPI_SWIGLU ? (n0 + wn * WN) / 2 : n0 + wn * WN);
+  float* E = reinterpret_cast<float*>(smem_raw) + wave * 16 * EP;
+  const bool vec_ok = (ldc % VW) == 0 && ((reinterpret_cast<uintptr_t>(Cv) & 15) == 0);
 #pragma unroll
-    for (int i = 0; i < MI; i++)
+  for (int i = 0; i < MI; i++) {
+    const int row_base = m0 + wm * WM + i * 16;
 #pragma unroll
-      for (int j = 0; j < NI; j += 2) {
-        int f = ((n0 + wn * WN) / 32 + j / 2) * 16 + (lane & 15);
+    for (int jj = 0; jj < OJ; jj++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          int row = rbase + i * 16 + r;
-          if (row < M && 2 * f < N) {
-            float gte = acc[i][j][r], up = acc[i][j + 1][r];
-            C[(int64_t)row * ldc + f] = from_f32<TO>(silu(gte) * up);
+      for (int r = 0; r < 4; r++) {
+        float v;
+        if constexpr (EPI == EPI_SWIGLU) v = silu(acc[i][2 * jj][r]) * acc[i][2 * jj + 1][r];
+        else v = acc[i][jj][r];
+        E[(4 * (lane >> 4) + r) * EP + jj * 16 + (lane & 15)] = v;
+      }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wavefront's LDS writes are done
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int pass = 0; pass < 16 / RPP; pass++) {
+      const int rr = pass * RPP + lane / LPR, cc = (lane % LPR) * VW;
+      const int row = row_base + rr, col = col0 + cc;
+      const float* e = E + rr * EP + cc;
+      if (row < M) {
+        if (vec_ok && col + VW <= n_out) {
+          if constexpr (EPI == EPI_ADD) {
+            f32x4* C = reinterpret_cast<f32x4*>(reinterpret_cast<float*>(Cv) + (int64_t)row * ldc + col);
+            *C = *C + *reinterpret_cast<const f32x4*>(e);
+          } else if constexpr (OUT_BF16) {
+            u32x4 pk;
+#pragma unroll
+            for (int q = 0; q < 4; q++) pk[q] = pack_bf16x2(e[2 * q], e[2 * q + 1]);
+            *reinterpret_cast<u32x4*>(reinterpret_cast<TO*>(Cv) + (int64_t)row * ldc + col) = pk;
+          } else {
+            *reinterpret_cast<f32x4*>(reinterpret_cast<float*>(Cv) + (int64_t)row * ldc + col) =
+                *reinterpret_cast<const f32x4*>(e);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < VW; q++) {
+            if (col + q >= n_out) break;
+            if constexpr (EPI == EPI_ADD) reinterpret_cast<float*>(Cv)[(int64_t)row * ldc + col + q] += e[q];
+            else reinterpret_cast<TO*>(Cv)[(int64_t)row * ldc + col + q] = from_f32<TO>(e[q]);
           }
         }
       }
-  } else {
-#pragma unroll
-    for (int i = 0; i < MI; i++)
-#pragma unroll
-      for (int j = 0; j < NI; j++)
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          int row = rbase + i * 16 + r, col = cbase + j * 16;
-          if (row < M && col < N) {
-            if constexpr (EPI == EPI_ADD) {
-              float* C = reinterpret_cast<float*>(Cv);
-              C[(int64_t)row * ldc + col] += acc[i][j][r];
-            } else {
-              TO* C = reinterpret_cast<TO*>(Cv);
-              C[(int64_t)row * ldc + col] = from_f32<TO>(acc[i][j][r]);
-            }
-          }
-        }
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // the slab's LDS reads are done before the next slab's writes
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -329,8 +354,9 @@ int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   auto it = tuned().find({dt, epi, s.N, s.K, mbucket(s.M)});
   if (it != tuned().end() && gemm_tile_ok(dt, it->second, s, epi)) return it->second;
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
-  if (s.M <= 128) return 3;
-  return 0;
+  if (s.M <= 128) return 3;        // 64x128
+  if (s.M < 8192) return 7;        // 128x128, 4 wavefronts
+  return 11;                       // 256x256, 8 wavefronts of 64x128
 }
 
 }  // namespace kvop
