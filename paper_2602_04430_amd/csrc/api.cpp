@@ -1549,6 +1549,14 @@ kvop_status kvop_tuning_import(const char* text) {
   return KVOP_OK;
 }
 
+kvop_status kvop_set_attention_kernel(int32_t variant) {
+  if (variant < -1 || variant > 2) return fail(KVOP_EINVAL, "attention kernel variant must be -1 .. 2");
+  attention_set_impl(variant);
+  return KVOP_OK;
+}
+
+int32_t kvop_get_attention_kernel(void) { return attention_get_impl(); }
+
 kvop_status kvop_set_wave_rows(int64_t rows) {
   if (rows < 64) return fail(KVOP_EINVAL, "wave must hold at least 64 rows");
   g_wave_rows = rows;

@@ -468,8 +468,14 @@ static hipError_t launch_kv(int D, const AttnArgs& a, hipStream_t st) {
   }
 }
 
+static int g_attn_impl = -1;
+void attention_set_impl(int impl) { g_attn_impl = impl; }
+int attention_get_impl() { return g_attn_impl; }
+
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st) {
   if (a.n_work <= 0) return hipSuccess;
+  if (g_attn_impl >= 0 && cdt == DT_BF16 && (kvdt == DT_BF16 || kvdt == DT_FP8) && (D == 64 || D == 128))
+    return attention_dma(kvdt, D, g_attn_impl, a, st);
   if (a.counter && a.persistent_wgs < 1) return hipErrorInvalidValue;
   if (a.G * a.Pmax > 64 || a.G < 1 || a.Pmax < 1) return hipErrorInvalidValue;
   if (cdt == DT_F32) {

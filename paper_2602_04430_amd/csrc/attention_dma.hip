@@ -1,0 +1,561 @@
+// Attention over gathered cache rows with direct global -> LDS loads (BF16 compute path).
+//
+// Same work decomposition and arithmetic as the register-staged kernel in attention.hip:
+// one workgroup of 4 wavefronts per (work item, kv head); scores computed transposed,
+// S^T = K Q^T, so that every accumulator of a lane belongs to one query; online softmax in
+// FP32 on raw scores with the 1/sqrt(D) scale folded into the exponent; O^T = V^T P^T.
+// The difference is how key/value tiles reach LDS: with global_load_lds every lane names
+// one 16-byte chunk of a cached row anywhere in HBM and the chunk lands in LDS at the
+// lane's slot, so a gathered tile costs no registers and up to NS tiles are in flight per
+// workgroup.  Completion is tracked with explicit vmcnt waits: every wavefront issues the
+// same number of vector-memory operations per tile.
+//
+// LDS layout of a tile part (K or V): rows in the source dtype (FP8 cache rows, BF16
+// cache or own rows), chunk c of row r at slot c ^ swz(r).  The K swizzle spreads the 16
+// rows read at one chunk by an S^T operand over distinct banks; the V swizzle does the
+// same for the 8 rows x 2 chunks of a transposed read.  V^T operands come from
+// ds_read_b64_tr_b16 (BF16 rows) or ds_read_b64_tr_b8 (FP8 rows) without a transposing
+// copy; FP8 values are widened with the hardware FP8 -> BF16 conversion (exact: every E4M3
+// value is a BF16 value) and their per-16-row block scales multiply scores and
+// probabilities as in the register-staged kernel.
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace kvop {
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef short v4i16_t __attribute__((ext_vector_type(4)));
+typedef int v2i32_t __attribute__((ext_vector_type(2)));
+
+template <typename TKV, int D, int KT_, int NS_>
+struct DmaCfg {
+  static constexpr bool FP8 = sizeof(TKV) == 1;
+  static constexpr int KT = KT_;                     // keys per cache tile
+  static constexpr int NS = NS_;                     // stages (tiles resident in LDS)
+  static constexpr int RBC = D * (int)sizeof(TKV);   // bytes per cached row
+  static constexpr int RBO = D * 2;                  // bytes per own (BF16) row
+  static constexpr int KTO = FP8 ? KT / 2 : KT;      // keys per own tile: the same bytes as a cache tile
+  static constexpr int CHC = RBC / 16, CHO = RBO / 16;
+  static constexpr int REGION = KT * RBC;            // bytes of the K (or V) part of a tile
+  static_assert(KT * RBC == KTO * RBO, "cache and own tiles move the same bytes");
+  static constexpr int NJ = 2 * REGION / 16 / 256;   // chunk loads per thread per tile
+  static constexpr int NR = NJ / 2;                  // rows per thread per tile (K and V chunks share them)
+  static_assert(NJ >= 2 && NJ % 2 == 0, "tile split");
+  static constexpr int META = 3 * 64 * 4;            // ksc | vsc | unused (64 slots each)
+  static constexpr int STAGE = 2 * REGION + META;
+  static constexpr int RING = NS * STAGE;            // row-number ring: NS + 1 slots of 64
+  static constexpr int DESC = RING + (NS + 1) * 64 * 4;  // 3 source descriptors
+  static constexpr int LDS = DESC + 3 * 64;
+  static constexpr int LDS_TOTAL = LDS;
+  // vmcnt that leaves only the newest tile's chunk + metadata loads outstanding
+  static constexpr int WAIT = NS >= 3 ? NJ + 1 : 0;
+  static_assert(NJ + 1 <= 15, "vmcnt immediates");
+  static_assert(NS == 2 || NS == 3, "stages");
+};
+
+// log2(16 / CH): consecutive rows that share one 256-byte bank line
+template <int CH> struct RowShift {
+  static constexpr int v = CH >= 16 ? 0 : (CH == 8 ? 1 : (CH == 4 ? 2 : 3));
+};
+template <int CH> __device__ inline int swz_k(int r) { return (r >> RowShift<CH>::v) & (CH - 1); }
+template <int CH> __device__ inline int swz_v(int r) { return CH >= 4 ? 2 * ((r >> RowShift<CH>::v) & (CH / 2 - 1)) : 0; }
+
+template <int N> __device__ inline void vm_wait() {
+  static_assert(N >= 0 && N <= 63, "vmcnt range");
+  // gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14, expcnt 6:4 (7: no wait), lgkmcnt 11:8 (15: no wait)
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+__device__ inline u32x4 fp8x8_to_bf16x8(uint32_t lo, uint32_t hi) {
+  u32x4 r;
+  r[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, false));
+  r[1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, true));
+  r[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, false));
+  r[3] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, true));
+  return r;
+}
+
+// V^T operand from an FP8 V tile: lane (qi, g4) needs V[key][d = 16 i + qi] for the keys of
+// its K slots (32 b2 + 4 g4 + 0..3, then + 16), widened to BF16.
+template <int CH, int RB>
+__device__ inline u32x4 fp8_vt_fragment(const uint8_t* Vp, int b2, int g4, int qi, int i) {
+  const int d = 16 * i + qi;
+  uint32_t lo = 0, hi = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int k0 = 32 * b2 + 4 * g4 + j, k1 = k0 + 16;
+    const uint32_t c0 = Vp[k0 * RB + (((d >> 4) ^ swz_v<CH>(k0)) * 16) + (d & 15)];
+    const uint32_t c1 = Vp[k1 * RB + (((d >> 4) ^ swz_v<CH>(k1)) * 16) + (d & 15)];
+    lo |= c0 << (8 * j);
+    hi |= c1 << (8 * j);
+  }
+  return fp8x8_to_bf16x8(lo, hi);
+}
+
+// ds_read_b64_tr_b16 as inline assembly.  The builtin form makes the compiler wait for every
+// direct-to-LDS load in flight (vmcnt(0)) before it, since it cannot tell which LDS bytes
+// the read touches.  The assembly form is followed by an explicit lgkmcnt(0) wait; the
+// caller reads V only from stages whose loads have completed (checked by the tile wait).
+// The result may only be used after lgkm_wait_all() has taken it as an operand.
+__device__ inline u32x2 ds_read_tr16(const uint8_t* p) {
+  const uint32_t addr = (uint32_t)reinterpret_cast<uintptr_t>(p);
+  u32x2 v;
+  asm volatile("ds_read_b64_tr_b16 %0, %1" : "=v"(v) : "v"(addr) : "memory");
+  return v;
+}
+// lgkmcnt(0), tied to the values it guards so that no use is scheduled above it
+template <int N> __device__ inline void lgkm_wait_all(u32x2 (&v)[N]);
+template <> __device__ inline void lgkm_wait_all<8>(u32x2 (&v)[8]) {
+  asm volatile("s_waitcnt lgkmcnt(0)"
+               : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+               :
+               : "memory");
+}
+template <> __device__ inline void lgkm_wait_all<16>(u32x2 (&v)[16]) {
+  asm volatile("s_waitcnt lgkmcnt(0)"
+               : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+                 "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+               :
+               : "memory");
+}
+
+// plain global load (global_load, not flat: a flat load also counts in lgkmcnt)
+template <typename T> __device__ inline T gload(const T* p) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) T*>(reinterpret_cast<uintptr_t>(p));
+}
+
+struct __attribute__((aligned(8))) DmaSrc {
+  const uint8_t* k;     // row 0 of the keys (bytes)
+  const uint8_t* v;
+  int64_t pitch;        // bytes between rows
+  const int32_t* idx;   // retained list or null (rows 0..n-1)
+  const float* ksc;     // FP8 block scales (per 16 rows) or null
+  const float* vsc;
+  int n, clampL, pos_add;
+};
+static_assert(sizeof(DmaSrc) <= 64, "descriptor slot");
+
+template <typename TKV, int D, int KT, int NS>
+__device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
+  using C = DmaCfg<TKV, D, KT, NS>;
+  constexpr int NQ = D / 32;                 // 32-deep K steps of S^T
+  constexpr int ND = D / 16;                 // 16-wide d blocks of the output
+  constexpr int NB = KT / 16;                // 16-key blocks of a cache tile
+  constexpr bool FP8 = C::FP8;
+
+  const int Hkv = a.Hkv;
+  const int h = unit % Hkv;
+  const AttnWork w = a.work[unit / Hkv];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int qi = lane & 15, g4 = lane >> 4;
+  const int r = wave * 16 + qi;
+  const int gq = r / a.Pmax, p = r % a.Pmax;
+  const bool qvalid = gq < a.G && p < w.n_q;
+  const bool wave_active = __any(qvalid);
+  const int hq = h * a.G + (gq < a.G ? gq : 0);
+  const int qpos = w.q_pos0 + p;
+  const int64_t qrow = (int64_t)w.q_row0 + (qvalid ? p : 0);
+
+  // ---- query fragments (B operand of S^T); qa: rotated for document B (joins)
+  u32x4 qf[NQ], qa[NQ];
+  const bool has_b = w.n_b > 0;
+  {
+    const bf16_t* q = reinterpret_cast<const bf16_t*>(a.q) + qrow * a.q_stride + hq * D;
+    const bf16_t* q2 = reinterpret_cast<const bf16_t*>(a.q_alt ? a.q_alt : a.q) + qrow * a.q_stride + hq * D;
+#pragma unroll
+    for (int k = 0; k < NQ; k++) {
+      const int d0 = 32 * k + 8 * g4;
+      qf[k] = qvalid ? *reinterpret_cast<const u32x4*>(q + d0) : u32x4{0, 0, 0, 0};
+      qa[k] = (qvalid && has_b) ? *reinterpret_cast<const u32x4*>(q2 + d0) : u32x4{0, 0, 0, 0};
+    }
+  }
+
+  // ---- key sources: 0 = document A, 1 = document B, 2 = own rows.  Three separate
+  // variables selected field by field (a dynamically indexed local array would live in
+  // scratch memory, and a scratch load waits behind every tile load in flight).
+  auto init_doc = [&](DmaSrc& s, int64_t off, int L, int64_t il, int n, int pos_add) {
+    s.n = n;
+    s.clampL = max(L, 1);
+    s.pos_add = pos_add;
+    s.idx = il >= 0 ? a.idx + il : nullptr;
+    s.pitch = C::RBC;
+    s.ksc = s.vsc = nullptr;
+    s.k = s.v = a.pool;
+    if (n > 0) {
+      const uint8_t* base = a.pool + off;
+      const int64_t kv_elems = (int64_t)L * D;
+      const int64_t head_off = ((int64_t)(a.layer * Hkv + h) * 2) * kv_elems;
+      s.k = base + head_off * (int64_t)sizeof(TKV);
+      s.v = s.k + kv_elems * (int64_t)sizeof(TKV);
+      if constexpr (FP8) {
+        const int nblk = (L + 15) >> 4;
+        const float* sb = reinterpret_cast<const float*>(base + (int64_t)2 * a.n_layers * Hkv * kv_elems);
+        s.ksc = sb + ((int64_t)(a.layer * Hkv + h) * 2) * nblk;
+        s.vsc = s.ksc + nblk;
+      }
+    }
+  };
+  DmaSrc src0, src1, src2;
+  init_doc(src0, w.off_a, w.L_a, w.idx_a, w.n_a, 0);
+  init_doc(src1, w.off_b, w.L_b, w.idx_b, w.n_b, w.L_a);
+  {
+    DmaSrc& s = src2;
+    s.n = w.n_own;
+    s.clampL = max(w.n_own, 1);
+    s.pos_add = w.own_pos0;
+    s.idx = nullptr;
+    s.ksc = s.vsc = nullptr;
+    s.pitch = a.own_stride * 2;
+    const uint8_t* ob = reinterpret_cast<const uint8_t*>(a.own) + (int64_t)w.own_row0 * s.pitch;
+    s.k = ob + (int64_t)(a.own_kcol + h * D) * 2;
+    s.v = ob + (int64_t)(a.own_vcol + h * D) * 2;
+  }
+  const int TA = (src0.n + KT - 1) / KT, TB = (src1.n + KT - 1) / KT;
+  const int TO = (src2.n + C::KTO - 1) / C::KTO;
+  // The three descriptors go to LDS once; the issuing and the computing side each keep a
+  // register copy of the current source and reload it from LDS when their tile index
+  // crosses into the next source (a runtime-selected local would live in scratch memory,
+  // and a scratch load waits behind every tile load in flight).
+  DmaSrc* ldsrc = reinterpret_cast<DmaSrc*>(smem + C::DESC);
+  if (tid == 0) ldsrc[0] = src0;
+  if (tid == 1) ldsrc[1] = src1;
+  if (tid == 2) ldsrc[2] = src2;
+  vm_wait<0>();  // the query fragments have arrived (the loop's waits count tile loads only)
+  __syncthreads();
+  const int T = TA + TB + TO;
+  // a valid address for loads whose value is not used (keeps the per-tile load count fixed)
+  const int32_t* dummy = reinterpret_cast<const int32_t*>(a.work + unit / Hkv);
+
+  auto tile_src = [&](int ti, int& sidx, int& t0) {
+    if (ti < TA) { sidx = 0; t0 = ti * KT; }
+    else if (ti < TA + TB) { sidx = 1; t0 = (ti - TA) * KT; }
+    else { sidx = 2; t0 = (ti - TA - TB) * C::KTO; }
+  };
+
+  // Row numbers of retained lists reach LDS by direct loads too (one 4-byte load per key,
+  // lane = key), one step before the tile's chunks are issued, into a ring of NS + 1
+  // slots: the loop then holds no register-destination memory load, so the only waits on
+  // memory are the explicit ones below.  Ring slot of tile X: X % (NS + 1).
+  int* ring = reinterpret_cast<int*>(smem + C::RING);
+  int iss_sidx = -1, cmp_sidx = -1;
+  DmaSrc iss = src0, cmp = src0;
+  auto issue_src = [&](int sidx) -> const DmaSrc& {
+    if (sidx != iss_sidx) {
+      iss = ldsrc[sidx];
+      iss_sidx = sidx;
+    }
+    return iss;
+  };
+  auto issue_rows = [&](int ti) {
+    int sidx, t0;
+    tile_src(ti, sidx, t0);
+    const DmaSrc& s = issue_src(sidx);
+    const int32_t* g = s.idx ? s.idx + min(t0 + lane, s.n - 1) : dummy;
+    __builtin_amdgcn_global_load_lds(g, (lds_void_t*)(ring + (ti % (NS + 1)) * 64), 4, 0, 0);
+  };
+  // chunk loads of tile ti into stage st, then one metadata load per wavefront (key =
+  // lane): wave 0 the K block scales, wave 1 the V block scales, waves 2-3 none (a load of
+  // an unused word keeps the count per wavefront the same)
+  auto issue_tile = [&](int ti, int st) {
+    int sidx, t0;
+    tile_src(ti, sidx, t0);
+    const DmaSrc& s = issue_src(sidx);
+    const int* rws = ring + (ti % (NS + 1)) * 64;
+    uint8_t* sb = smem + st * C::STAGE;
+    const bool own = sidx == 2;
+    const int ch = own ? C::CHO : C::CHC;
+#pragma unroll
+    for (int j = 0; j < C::NJ; j++) {
+      const int jr = j % C::NR;
+      const bool is_v = j >= C::NR;
+      const int f = 256 * jr + tid;              // chunk index inside the part
+      const int rr = f / ch, slot = f % ch;
+      const int t = min(t0 + rr, s.n - 1);
+      const int row = min(max(s.idx ? rws[rr] : t, 0), s.clampL - 1);
+      int sw;
+      if (own) sw = is_v ? swz_v<C::CHO>(rr) : swz_k<C::CHO>(rr);
+      else sw = is_v ? swz_v<C::CHC>(rr) : swz_k<C::CHC>(rr);
+      const uint8_t* g = (is_v ? s.v : s.k) + (int64_t)row * s.pitch + (slot ^ sw) * 16;
+      uint8_t* l = sb + (is_v ? C::REGION : 0) + (256 * jr + 64 * wave) * 16;
+      __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 16, 0, 0);
+    }
+    float* meta = reinterpret_cast<float*>(sb + 2 * C::REGION);
+    const int row = min(max(s.idx ? rws[lane] : min(t0 + lane, s.n - 1), 0), s.clampL - 1);
+    const void* g = dummy;
+    if (wave == 0 && s.ksc) g = s.ksc + (row >> 4);
+    if (wave == 1 && s.vsc) g = s.vsc + (row >> 4);
+    __builtin_amdgcn_global_load_lds(g, (lds_void_t*)(meta + min(wave, 2) * 64), 4, 0, 0);
+  };
+
+  float m_run = -INFINITY, l_run = 0.f;
+  f32x4 o[ND];
+#pragma unroll
+  for (int i = 0; i < ND; i++) o[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // Prologue: rows of tile 0; then for q = 0 .. NS-2: rows of tile q + 1, chunks of tile q.
+  // Waiting until only the newest chunk loads (NJ + 1) are outstanding guarantees the rows
+  // issued just before them.
+  if (T > 0) {
+    issue_rows(0);
+    vm_wait<0>();
+    __builtin_amdgcn_s_barrier();
+  }
+#pragma unroll
+  for (int q = 0; q < NS - 1; q++) {
+    if (q < T) {
+      if (q + 1 < T) issue_rows(q + 1);
+      issue_tile(q, q);
+      vm_wait<C::NJ + 1>();
+      __builtin_amdgcn_s_barrier();
+    }
+  }
+
+  for (int ti = 0; ti < T; ti++) {
+    // Tile ti and the rows of tile ti + NS - 1 have landed once only the previous step's
+    // chunk loads may be outstanding (NS = 3; NS = 2 waits for everything); if that step
+    // issued no chunks, wait for everything.  Then a bare s_barrier makes every
+    // wavefront's loads visible and marks tile ti - 1 consumed (a fence would wait for
+    // the loads still in flight).
+    if (ti + NS - 2 < T) vm_wait<C::WAIT>();
+    else vm_wait<0>();
+    __builtin_amdgcn_s_barrier();
+    if (ti + NS < T) issue_rows(ti + NS);
+    if (ti + NS - 1 < T) issue_tile(ti + NS - 1, (ti + NS - 1) % NS);
+
+    int sidx, t0;
+    tile_src(ti, sidx, t0);
+    if (sidx != cmp_sidx) {
+      cmp = ldsrc[sidx];
+      cmp_sidx = sidx;
+    }
+    const DmaSrc& s = cmp;
+    const bool own = sidx == 2;
+    const bool tile_fp8 = FP8 && !own;
+    const int nbt = (own ? C::KTO : KT) / 16;  // 16-key blocks present in this tile
+    const uint8_t* sb = smem + (ti % NS) * C::STAGE;
+    const uint8_t* Kp = sb;
+    const uint8_t* Vp = sb + C::REGION;
+    const float* ksc_s = reinterpret_cast<const float*>(sb + 2 * C::REGION);
+    const float* vsc_s = ksc_s + 64;
+    const int* rows_s = ring + (ti % (NS + 1)) * 64;
+
+    // document B is scored with the queries rotated at (position - L_A)
+    if (has_b && (ti == TA || ti == TA + TB)) {
+#pragma unroll
+      for (int k = 0; k < NQ; k++) {
+        const u32x4 tmp = qf[k];
+        qf[k] = qa[k];
+        qa[k] = tmp;
+      }
+    }
+    if (!wave_active) continue;
+
+    // ---- scores S^T[key][query]: lane holds keys 16 b + 4 g4 + t of query column qi
+    f32x4 sc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      sc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (b >= nbt) continue;
+      const int kr = 16 * b + qi;
+#pragma unroll
+      for (int k = 0; k < NQ; k++) {
+        u32x4 kf;
+        if (tile_fp8) {
+          const int pc = 4 * k + g4;  // 8-byte piece of the FP8 row
+          const u32x2 raw = *reinterpret_cast<const u32x2*>(Kp + kr * C::RBC + ((pc >> 1) ^ swz_k<C::CHC>(kr)) * 16 +
+                                                           (pc & 1) * 8);
+          kf = fp8x8_to_bf16x8(raw[0], raw[1]);
+        } else if (own) {
+          kf = *reinterpret_cast<const u32x4*>(Kp + kr * C::RBO + ((4 * k + g4) ^ swz_k<C::CHO>(kr)) * 16);
+        } else {
+          kf = *reinterpret_cast<const u32x4*>(Kp + kr * C::RBC + ((4 * k + g4) ^ swz_k<C::CHC>(kr)) * 16);
+        }
+        sc[b] = mfma_bf16(__builtin_bit_cast(u16x8, kf), __builtin_bit_cast(u16x8, qf[k]), sc[b]);
+      }
+    }
+    // ---- online softmax (FP32).  Keys past the source's end and keys after the query's
+    // position are masked; only tiles that can hold such keys test positions.
+    const int n_here = s.n - t0;
+    const bool need_mask = own || n_here < nbt * 16 || (!s.idx && t0 + nbt * 16 - 1 + s.pos_add > w.q_pos0) ||
+                           (s.idx && rows_s[nbt * 16 - 1] + s.pos_add > w.q_pos0);
+    float mx = -INFINITY;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const int key = 16 * b + 4 * g4 + t;
+        float v = sc[b][t];
+        if (tile_fp8) v *= ksc_s[key];
+        if (b >= nbt) {
+          v = -INFINITY;
+        } else if (need_mask) {
+          const int kpos = key < n_here ? (s.idx ? rows_s[key] : t0 + key) + s.pos_add : 0x7fffffff;
+          if (!(kpos <= qpos)) v = -INFINITY;
+        }
+        sc[b][t] = v;
+        mx = fmaxf(mx, v);
+      }
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    const float c = a.scale_log2;
+    const float m_new = fmaxf(m_run, mx);
+    const float mc = m_new == -INFINITY ? 0.f : m_new * c;
+    const float alpha = __builtin_amdgcn_exp2f(m_run * c - mc);  // 0 when m_run = -inf
+    float psum = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const float pv = __builtin_amdgcn_exp2f(fmaf(sc[b][t], c, -mc));  // exp2(-inf) = 0
+        sc[b][t] = pv;
+        psum += pv;
+      }
+    l_run = l_run * alpha + psum;
+    m_run = m_new;
+#pragma unroll
+    for (int i = 0; i < ND; i++) o[i] *= alpha;
+
+    // ---- O^T[d][query] += V^T[d][key] P^T[key][query].  K slots 0..3 of lane group g4 are
+    // keys 32 b2 + 4 g4 + t, slots 4..7 keys 32 b2 + 16 + 4 g4 + t.
+#pragma unroll
+    for (int b2 = 0; b2 < NB / 2; b2++) {
+      if (2 * b2 >= nbt) continue;
+      u32x4 pb;
+#pragma unroll
+      for (int t = 0; t < 4; t += 2) {
+        float p0 = sc[2 * b2][t], p0n = sc[2 * b2][t + 1];
+        float p1 = sc[2 * b2 + 1][t], p1n = sc[2 * b2 + 1][t + 1];
+        if (tile_fp8) {
+          p0 *= vsc_s[32 * b2 + 4 * g4 + t];
+          p0n *= vsc_s[32 * b2 + 4 * g4 + t + 1];
+          p1 *= vsc_s[32 * b2 + 16 + 4 * g4 + t];
+          p1n *= vsc_s[32 * b2 + 16 + 4 * g4 + t + 1];
+        }
+        pb[t / 2] = pack_bf16x2(p0, p0n);
+        pb[2 + t / 2] = pack_bf16x2(p1, p1n);
+      }
+      // lane (qi, g4) reads V[keys 32 b2 + 4 g4 + 0..3 (+16)][d = 16 i + qi]
+      const int vr0 = 32 * b2 + 4 * g4 + (qi >> 2), vr1 = vr0 + 16;
+      if (tile_fp8) {
+#pragma unroll
+        for (int i = 0; i < ND; i++) {
+          const u32x4 va = fp8_vt_fragment<C::CHC, C::RBC>(Vp, b2, g4, qi, i);
+          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
+        }
+      } else {
+        // 16-bit transposed reads: lane (qi, g4) addresses row vr (qi / 4 selects the key),
+        // columns 16 i + 4 (qi % 4) .. +3; lane qi receives column 16 i + qi of 4 rows
+        const int rb = own ? C::RBO : C::RBC;
+        const int s0 = own ? swz_v<C::CHO>(vr0) : swz_v<C::CHC>(vr0);
+        const int s1 = own ? swz_v<C::CHO>(vr1) : swz_v<C::CHC>(vr1);
+        u32x2 y[2 * ND];
+#pragma unroll
+        for (int i = 0; i < ND; i++) {
+          const int cch = (16 * i + 4 * (qi & 3)) >> 3, half = qi & 1;
+          y[2 * i] = ds_read_tr16(Vp + vr0 * rb + (cch ^ s0) * 16 + half * 8);
+          y[2 * i + 1] = ds_read_tr16(Vp + vr1 * rb + (cch ^ s1) * 16 + half * 8);
+        }
+        lgkm_wait_all<2 * ND>(y);
+#pragma unroll
+        for (int i = 0; i < ND; i++) {
+          const u32x4 va = u32x4{y[2 * i][0], y[2 * i][1], y[2 * i + 1][0], y[2 * i + 1][1]};
+          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
+        }
+      }
+    }
+  }
+
+  // ---- normalise and store: lane holds O[query qi][d = 16 i + 4 g4 + t]
+  float l_tot = l_run + __shfl_xor(l_run, 16, 64);
+  l_tot += __shfl_xor(l_tot, 32, 64);
+  __syncthreads();  // LDS reused by the workgroup's next unit
+  if (!qvalid) return;
+  const float inv = l_tot > 0.f ? 1.f / l_tot : 0.f;
+  bf16_t* out = reinterpret_cast<bf16_t*>(a.out) + qrow * a.out_stride + hq * D;
+#pragma unroll
+  for (int i = 0; i < ND; i++) {
+    const int d0 = 16 * i + 4 * g4;
+    u32x2 pk;
+    pk[0] = pack_bf16x2(o[i][0] * inv, o[i][1] * inv);
+    pk[1] = pack_bf16x2(o[i][2] * inv, o[i][3] * inv);
+    *reinterpret_cast<u32x2*>(out + d0) = pk;
+  }
+}
+
+// One workgroup per unit.
+template <typename TKV, int D, int KT, int NS>
+__global__ __launch_bounds__(256) void attn_dma_kernel(AttnArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
+  attn_dma_unit<TKV, D, KT, NS>(a, blockIdx.x, dma_smem);
+}
+
+// Persistent form: a fixed grid takes units from a device counter (zeroed by the caller
+// before the launch) until every unit is taken; every workgroup exits once the counter
+// passes the unit count, so the grid always drains.
+template <typename TKV, int D, int KT, int NS>
+__global__ __launch_bounds__(256) void attn_dma_persistent_kernel(AttnArgs a) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
+  __shared__ int next;
+  const int total = a.n_work * a.Hkv;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int unit = next;
+    __syncthreads();
+    if (unit >= total) break;
+    attn_dma_unit<TKV, D, KT, NS>(a, unit, dma_smem);
+  }
+}
+
+template <typename TKV, int D, int KT, int NS>
+static hipError_t launch_dma(const AttnArgs& a, hipStream_t st) {
+  using C = DmaCfg<TKV, D, KT, NS>;
+  const int64_t units = (int64_t)a.n_work * a.Hkv;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)attn_dma_kernel<TKV, D, KT, NS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_TOTAL);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)attn_dma_persistent_kernel<TKV, D, KT, NS>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_TOTAL);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (a.counter) {
+    hipLaunchKernelGGL((attn_dma_persistent_kernel<TKV, D, KT, NS>),
+                       dim3((unsigned)std::min<int64_t>(units, a.persistent_wgs)), dim3(256), C::LDS_TOTAL, st, a);
+  } else {
+    hipLaunchKernelGGL((attn_dma_kernel<TKV, D, KT, NS>), dim3((unsigned)units), dim3(256), C::LDS_TOTAL, st, a);
+  }
+  return hipGetLastError();
+}
+
+// variant: 0 = KT 64 / 2 stages, 1 = KT 64 / 3 stages, 2 = KT 32 / 3 stages
+// (D = 64 has no 32-key variant: its FP8 tile would be under one chunk load per thread)
+template <typename TKV, int D>
+static hipError_t launch_dma_variant(int variant, const AttnArgs& a, hipStream_t st) {
+  if (variant == 0) return launch_dma<TKV, D, 64, 2>(a, st);
+  if constexpr (D == 64) return launch_dma<TKV, D, 64, 3>(a, st);
+  else {
+    if (variant == 1) return launch_dma<TKV, D, 64, 3>(a, st);
+    return launch_dma<TKV, D, 32, 3>(a, st);
+  }
+}
+
+hipError_t attention_dma(int kvdt, int D, int variant, const AttnArgs& a, hipStream_t st) {
+  if (a.n_work <= 0) return hipSuccess;
+  if (a.counter && a.persistent_wgs < 1) return hipErrorInvalidValue;
+  if (a.G * a.Pmax > 64 || a.G < 1 || a.Pmax < 1) return hipErrorInvalidValue;
+  if (kvdt == DT_BF16) {
+    if (D == 128) return launch_dma_variant<bf16_t, 128>(variant, a, st);
+    if (D == 64) return launch_dma_variant<bf16_t, 64>(variant, a, st);
+  } else if (kvdt == DT_FP8) {
+    if (D == 128) return launch_dma_variant<fp8_t, 128>(variant, a, st);
+    if (D == 64) return launch_dma_variant<fp8_t, 64>(variant, a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace kvop

@@ -72,6 +72,12 @@ struct AttnArgs {
 };
 // cdt: compute/query dtype (f32 or bf16); kvdt: cache dtype (f32 with f32; bf16/fp8 with bf16)
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st);
+// BF16 compute with a BF16 or FP8 cache, D in {64, 128}: tiles fetched by direct global->LDS
+// loads.  variant: 0 = 64-key tiles / 2 stages, 1 = 64 / 3, 2 = 32 / 3.
+hipError_t attention_dma(int kvdt, int D, int variant, const AttnArgs& a, hipStream_t st);
+// attention kernel used by attention(): -1 = register-staged, else the attention_dma variant
+void attention_set_impl(int impl);
+int attention_get_impl();
 
 // ---------------------------------------------------------------- elementwise / small kernels
 // x[row] = embed[tok[row]] (embed in `dt`), FP32 output; ids clamped to [0, V)

@@ -79,6 +79,8 @@ _SIGS = {
     "kvop_proxy_infer": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
     "kvop_proxy_params": (C.c_int, [_P, _P, _P]),
     "kvop_set_wave_rows": (C.c_int, [C.c_int64]),
+    "kvop_set_attention_kernel": (C.c_int, [C.c_int32]),
+    "kvop_get_attention_kernel": (C.c_int32, []),
     "kvop_autotune": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.c_int32]),
     "kvop_tuning_export": (C.c_int32, [_P, C.c_int32]),
     "kvop_tuning_import": (C.c_int, [C.c_char_p]),
@@ -297,6 +299,14 @@ def kvop_proxy_params(proxy, out_dev, stream=None) -> None:
 
 def kvop_set_wave_rows(rows: int) -> None:
     _check(lib().kvop_set_wave_rows(int(rows)))
+
+
+def kvop_set_attention_kernel(variant: int) -> None:
+    _check(lib().kvop_set_attention_kernel(int(variant)))
+
+
+def kvop_get_attention_kernel() -> int:
+    return int(lib().kvop_get_attention_kernel())
 
 
 def kvop_mixed_eval(pool, ops, r: float, idx_dev, idx_offsets, handles, item_op, item_list, flags: int,

@@ -69,3 +69,13 @@ def test_tuning_table_text_roundtrip():
         K.kvop_tuning_import("1 2 11264 2048 17 no_such_tile\n")
     K.kvop_gemm_set_tile(K.KVOP_BF16, 2, 11264, 2048, 131072, 0)     # M=131072 -> bucket 17
     assert f"1 2 11264 2048 17 {K.kvop_gemm_tile_name(K.KVOP_BF16, 0)}" in K.kvop_tuning_export()
+
+
+def test_attention_kernel_knob_is_host_state_and_checked():
+    assert K.kvop_get_attention_kernel() == -1
+    for v in (0, 1, 2, -1):
+        K.kvop_set_attention_kernel(v)
+        assert K.kvop_get_attention_kernel() == v
+    with pytest.raises(K.KvopError):
+        K.kvop_set_attention_kernel(3)
+    assert K.kvop_get_attention_kernel() == -1
