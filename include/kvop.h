@@ -287,6 +287,10 @@ kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epilogue, int32_t N, int32
  * a BF16 cache. */
 kvop_status kvop_set_attention_kernel(int32_t variant);
 int32_t kvop_get_attention_kernel(void);
+/* Widen n FP8 (E4M3 fn) codes (device bytes) to BF16 bit patterns (device uint16) with the
+ * conversion the direct-load attention kernels apply to FP8 cache rows.  n > 0, a multiple
+ * of 8 (EINVAL otherwise).  Asynchronous on stream. */
+kvop_status kvop_debug_fp8_to_bf16(const uint8_t* codes_dev, int32_t n, uint16_t* out_dev, void* stream);
 /* Copy the cached keys (kv = 0) or values (kv = 1) of one document, one layer and one
  * kv head into out_dev as FP32 [L, head_dim] (FP8 entries decoded and scaled). */
 kvop_status kvop_debug_read_cache(kvop_pool* pool, kvop_handle handle, int32_t layer, int32_t kv_head, int32_t kv,

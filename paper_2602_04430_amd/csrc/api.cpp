@@ -1557,6 +1557,12 @@ kvop_status kvop_set_attention_kernel(int32_t variant) {
 
 int32_t kvop_get_attention_kernel(void) { return attention_get_impl(); }
 
+kvop_status kvop_debug_fp8_to_bf16(const uint8_t* codes_dev, int32_t n, uint16_t* out_dev, void* stream) {
+  if (!codes_dev || !out_dev || n <= 0 || n % 8) return fail(KVOP_EINVAL, "n must be a positive multiple of 8");
+  HIPTRY(fp8_widen(codes_dev, out_dev, n, (hipStream_t)stream));
+  return KVOP_OK;
+}
+
 kvop_status kvop_set_wave_rows(int64_t rows) {
   if (rows < 64) return fail(KVOP_EINVAL, "wave must hold at least 64 rows");
   g_wave_rows = rows;

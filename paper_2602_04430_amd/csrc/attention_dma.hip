@@ -61,6 +61,12 @@ template <int CH> struct RowShift {
 };
 template <int CH> __device__ inline int swz_k(int r) { return (r >> RowShift<CH>::v) & (CH - 1); }
 template <int CH> __device__ inline int swz_v(int r) { return CH >= 4 ? 2 * ((r >> RowShift<CH>::v) & (CH / 2 - 1)) : 0; }
+// V swizzle of FP8 rows (read by ds_read_b64_tr_b8: rows r, r + 1, r + 2, r + 3 and the
+// same + 16 at one chunk, for two lane groups): distinct (slot, bank line half) pairs
+template <int CH> __device__ inline int swz_v8(int r) {
+  if constexpr (CH >= 8) return ((r >> 1) & 3) | (((r >> 4) & 1) << 2);
+  else return ((r >> 2) & 1) | (((r >> 4) & 1) << 1);
+}
 
 template <int N> __device__ inline void vm_wait() {
   static_assert(N >= 0 && N <= 63, "vmcnt range");
@@ -77,23 +83,6 @@ __device__ inline u32x4 fp8x8_to_bf16x8(uint32_t lo, uint32_t hi) {
   return r;
 }
 
-// V^T operand from an FP8 V tile: lane (qi, g4) needs V[key][d = 16 i + qi] for the keys of
-// its K slots (32 b2 + 4 g4 + 0..3, then + 16), widened to BF16.
-template <int CH, int RB>
-__device__ inline u32x4 fp8_vt_fragment(const uint8_t* Vp, int b2, int g4, int qi, int i) {
-  const int d = 16 * i + qi;
-  uint32_t lo = 0, hi = 0;
-#pragma unroll
-  for (int j = 0; j < 4; j++) {
-    const int k0 = 32 * b2 + 4 * g4 + j, k1 = k0 + 16;
-    const uint32_t c0 = Vp[k0 * RB + (((d >> 4) ^ swz_v<CH>(k0)) * 16) + (d & 15)];
-    const uint32_t c1 = Vp[k1 * RB + (((d >> 4) ^ swz_v<CH>(k1)) * 16) + (d & 15)];
-    lo |= c0 << (8 * j);
-    hi |= c1 << (8 * j);
-  }
-  return fp8x8_to_bf16x8(lo, hi);
-}
-
 // ds_read_b64_tr_b16 as inline assembly.  The builtin form makes the compiler wait for every
 // direct-to-LDS load in flight (vmcnt(0)) before it, since it cannot tell which LDS bytes
 // the read touches.  The assembly form is followed by an explicit lgkmcnt(0) wait; the
@@ -105,8 +94,17 @@ __device__ inline u32x2 ds_read_tr16(const uint8_t* p) {
   asm volatile("ds_read_b64_tr_b16 %0, %1" : "=v"(v) : "v"(addr) : "memory");
   return v;
 }
+__device__ inline u32x2 ds_read_tr8(const uint8_t* p) {
+  const uint32_t addr = (uint32_t)reinterpret_cast<uintptr_t>(p);
+  u32x2 v;
+  asm volatile("ds_read_b64_tr_b8 %0, %1" : "=v"(v) : "v"(addr) : "memory");
+  return v;
+}
 // lgkmcnt(0), tied to the values it guards so that no use is scheduled above it
 template <int N> __device__ inline void lgkm_wait_all(u32x2 (&v)[N]);
+template <> __device__ inline void lgkm_wait_all<4>(u32x2 (&v)[4]) {
+  asm volatile("s_waitcnt lgkmcnt(0)" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]) : : "memory");
+}
 template <> __device__ inline void lgkm_wait_all<8>(u32x2 (&v)[8]) {
   asm volatile("s_waitcnt lgkmcnt(0)"
                : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
@@ -276,6 +274,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
       const int row = min(max(s.idx ? rws[rr] : t, 0), s.clampL - 1);
       int sw;
       if (own) sw = is_v ? swz_v<C::CHO>(rr) : swz_k<C::CHO>(rr);
+      else if (FP8) sw = is_v ? swz_v8<C::CHC>(rr) : swz_k<C::CHC>(rr);
       else sw = is_v ? swz_v<C::CHC>(rr) : swz_k<C::CHC>(rr);
       const uint8_t* g = (is_v ? s.v : s.k) + (int64_t)row * s.pitch + (slot ^ sw) * 16;
       uint8_t* l = sb + (is_v ? C::REGION : 0) + (256 * jr + 64 * wave) * 16;
@@ -439,9 +438,19 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
       // lane (qi, g4) reads V[keys 32 b2 + 4 g4 + 0..3 (+16)][d = 16 i + qi]
       const int vr0 = 32 * b2 + 4 * g4 + (qi >> 2), vr1 = vr0 + 16;
       if (tile_fp8) {
+        // 8-bit transposed reads: within a lane group, lane qi addresses key slot qi / 2
+        // (row 32 b2 + 4 g4 + (qi/2 < 4 ? qi/2 : 16 + qi/2 - 4)) at byte columns
+        // 16 i + 8 (qi % 2) .. +7; lane qi receives byte column 16 i + qi of the 8 rows
+        const int ks = qi >> 1;
+        const int vr = 32 * b2 + 4 * g4 + (ks < 4 ? ks : 12 + ks);
+        const int sv = swz_v8<C::CHC>(vr);
+        u32x2 y[ND];
+#pragma unroll
+        for (int i = 0; i < ND; i++) y[i] = ds_read_tr8(Vp + vr * C::RBC + ((i ^ sv) * 16) + (qi & 1) * 8);
+        lgkm_wait_all<ND>(y);
 #pragma unroll
         for (int i = 0; i < ND; i++) {
-          const u32x4 va = fp8_vt_fragment<C::CHC, C::RBC>(Vp, b2, g4, qi, i);
+          const u32x4 va = fp8x8_to_bf16x8(y[i][0], y[i][1]);
           o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
         }
       } else {
@@ -542,6 +551,22 @@ static hipError_t launch_dma_variant(int variant, const AttnArgs& a, hipStream_t
     if (variant == 1) return launch_dma<TKV, D, 64, 3>(a, st);
     return launch_dma<TKV, D, 32, 3>(a, st);
   }
+}
+
+// The attention kernels' FP8 -> BF16 widening applied to a code array (n a multiple of 8),
+// for an exhaustive check against the format's definition.
+__global__ void fp8_widen_kernel(const uint8_t* __restrict__ codes, uint16_t* __restrict__ out, int n8) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n8) return;
+  const u32x2 raw = *reinterpret_cast<const u32x2*>(codes + 8 * i);
+  *reinterpret_cast<u32x4*>(out + 8 * i) = fp8x8_to_bf16x8(raw[0], raw[1]);
+}
+
+hipError_t fp8_widen(const uint8_t* codes, uint16_t* out, int n, hipStream_t st) {
+  if (n <= 0 || n % 8) return hipErrorInvalidValue;
+  const int n8 = n / 8;
+  hipLaunchKernelGGL(fp8_widen_kernel, dim3((n8 + 255) / 256), dim3(256), 0, st, codes, out, n8);
+  return hipGetLastError();
 }
 
 hipError_t attention_dma(int kvdt, int D, int variant, const AttnArgs& a, hipStream_t st) {

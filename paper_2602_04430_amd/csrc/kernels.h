@@ -75,6 +75,8 @@ hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st
 // BF16 compute with a BF16 or FP8 cache, D in {64, 128}: tiles fetched by direct global->LDS
 // loads.  variant: 0 = 64-key tiles / 2 stages, 1 = 64 / 3, 2 = 32 / 3.
 hipError_t attention_dma(int kvdt, int D, int variant, const AttnArgs& a, hipStream_t st);
+// FP8 (E4M3) codes -> BF16 bits with the conversion the direct-load kernels use (n % 8 == 0)
+hipError_t fp8_widen(const uint8_t* codes, uint16_t* out, int n, hipStream_t st);
 // attention kernel used by attention(): -1 = register-staged, else the attention_dma variant
 void attention_set_impl(int impl);
 int attention_get_impl();

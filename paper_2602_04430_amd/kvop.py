@@ -81,6 +81,7 @@ _SIGS = {
     "kvop_set_wave_rows": (C.c_int, [C.c_int64]),
     "kvop_set_attention_kernel": (C.c_int, [C.c_int32]),
     "kvop_get_attention_kernel": (C.c_int32, []),
+    "kvop_debug_fp8_to_bf16": (C.c_int, [_P, C.c_int32, _P, _P]),
     "kvop_autotune": (C.c_int, [_P, C.c_int64, C.c_int32, _P, _P, C.c_int32]),
     "kvop_tuning_export": (C.c_int32, [_P, C.c_int32]),
     "kvop_tuning_import": (C.c_int, [C.c_char_p]),
@@ -307,6 +308,10 @@ def kvop_set_attention_kernel(variant: int) -> None:
 
 def kvop_get_attention_kernel() -> int:
     return int(lib().kvop_get_attention_kernel())
+
+
+def kvop_debug_fp8_to_bf16(codes_dev, out_dev, stream=None) -> None:
+    _check(lib().kvop_debug_fp8_to_bf16(_dptr(codes_dev), int(codes_dev.numel()), _dptr(out_dev), _stream(stream)))
 
 
 def kvop_mixed_eval(pool, ops, r: float, idx_dev, idx_offsets, handles, item_op, item_list, flags: int,

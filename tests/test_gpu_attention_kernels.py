@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import codecs
 from oracle import model as om
 from paper_2602_04430_amd import kvop as K
 from paper_2602_04430_amd import synth
@@ -119,3 +120,19 @@ def test_dma_attention_join_and_map_match_oracle(device, attention_kernel, varia
         if np.all(margins >= 2 * E):
             np.testing.assert_array_equal(tk[i], res.tokens)
     eng.close()
+
+
+def test_fp8_widening_is_exact_for_every_code(device):
+    """The hardware E4M3 -> BF16 conversion of the direct-load kernels, all 256 codes, bit for
+    bit against the format's definition (every E4M3 value is a BF16 value; NaN stays NaN)."""
+    codes = torch.arange(256, dtype=torch.uint8, device=device)
+    out = torch.empty(256, dtype=torch.int16, device=device)
+    K.kvop_debug_fp8_to_bf16(codes, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint16)
+    ref = codecs.e4m3_decode_table()
+    ref_bits = (codecs.bf16_round(ref.astype(np.float32)).view(np.uint32) >> 16).astype(np.uint16)
+    finite = np.isfinite(ref)
+    np.testing.assert_array_equal(got[finite], ref_bits[finite])
+    as_f = (got.astype(np.uint32) << 16).view(np.float32)
+    assert np.all(np.isnan(as_f[~finite]))
