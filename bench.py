@@ -419,6 +419,15 @@ def bench_mixed(args, K, synth, dev):
             K.kvop_op_eval(pool, opj, 1.0, sel_idx, L_off[nf + nm:], hs[nf + nm:], lj, dj)
         t_mode["separate_calls"] += timed(separate)
         compare(diff["separate_calls"], ref, outputs(reorder=True))
+        if g == 0:        # where the time goes: per-class profile of one eager call and of the separate calls
+            K.kvop_profile_start()
+            K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op, item_list, 0)
+            prof_mixed = {k: round(v[0], 1) for k, v in K.kvop_profile_stop().items()}
+            K.kvop_profile_start()
+            separate()
+            prof_sep = {k: round(v[0], 1) for k, v in K.kvop_profile_stop().items()}
+            log(f"profile (ms) eager mixed: {prof_mixed}")
+            log(f"profile (ms) separate calls: {prof_sep}")
         log(f"group {g}: {len(need)} docs, {nf}/{nm}/{nj} items, graph {t_mode['graph_persistent']:.0f} ms so far; "
             f"differences from the graph mode: {diff}")
         K.kvop_kv_release(pool, hsub)
@@ -435,6 +444,7 @@ def bench_mixed(args, K, synth, dev):
                        "groups": G, "items": n_items},
             "modes_items_per_s": {k: n_items / (v / 1e3) for k, v in t_mode.items()},
             "differences_from_graph_mode": diff, "wave_rows": WAVE_ROWS,
+            "profile_group0_ms": {"eager_mixed": prof_mixed, "separate_calls": prof_sep},
             "kv_build_s": t_build, "gemm_tiles": tiles}
     print(json.dumps(line), flush=True)
 

@@ -28,9 +28,10 @@ int64_t g_wave_rows = 131072;  // suffix rows per op_eval / mixed wave
 // ---- optional per-kernel-class timing: HIP events recorded on the caller's stream around
 // each launch while profiling is on; read back (synchronising) by kvop_profile_stop.
 enum ProfClass { PC_GEMM_QKV, PC_GEMM_O, PC_GEMM_GATEUP, PC_GEMM_DOWN, PC_ATTENTION, PC_ROPE_KV, PC_RMSNORM,
-                 PC_EMBED, PC_HEAD, PC_OTHER, PC_COUNT };
+                 PC_EMBED, PC_HEAD, PC_DECODE, PC_OTHER, PC_COUNT };
+// map_decode: one whole greedy decode step (all layers) of a map operator
 const char* kProfNames[PC_COUNT] = {"gemm_qkv", "gemm_o", "gemm_gate_up", "gemm_down", "attention", "rope_kv",
-                                    "rmsnorm", "embed", "head", "other"};
+                                    "rmsnorm", "embed", "head", "map_decode", "other"};
 struct Prof {
   bool on = false;
   bool capturing = false;  // no event records while a graph is being captured
@@ -948,6 +949,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, nullptr, orow, lg,
                     (int64_t)n_gen * ln, tk, n_gen, ntok, st));
     for (int t = 1; t < n_gen; t++) {
+        ProfScope decode_scope(PC_DECODE, st);
       // positions of the fed token: L + S + t - 1; it is own row S + t - 1 of its item
       std::vector<int32_t> pdec(B), ddst(B);
       for (int b = 0; b < B; b++) {
@@ -1342,6 +1344,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
                       (const int32_t*)(md + o_in[map_op]), orow, ops[map_op].logits_out_dev, (int64_t)n_gen * ln,
                       ops[map_op].tokens_out_dev, n_gen, ntok, st));
       for (int t = 1; t < n_gen; t++) {
+        ProfScope decode_scope(PC_DECODE, st);
         const int32_t* pd = (const int32_t*)(md + o_pd) + (size_t)(t - 1) * nm;
         const int32_t* dd = (const int32_t*)(md + o_dd) + (size_t)(t - 1) * nm;
         const AttnWork* dw = (const AttnWork*)(md + o_dw) + (size_t)(t - 1) * nm;

@@ -435,8 +435,10 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
         pb[t / 2] = pack_bf16x2(p0, p0n);
         pb[2 + t / 2] = pack_bf16x2(p1, p1n);
       }
-      // lane (qi, g4) reads V[keys 32 b2 + 4 g4 + 0..3 (+16)][d = 16 i + qi]
-      const int vr0 = 32 * b2 + 4 * g4 + (qi >> 2), vr1 = vr0 + 16;
+      // lane (qi, g4) reads V[keys 32 b2 + 4 g4 + 0..3 (+16)][d = 16 i + qi].  A tile with a
+      // single 16-key block in this pair (a 16-key own tile) has no rows +16: those keys
+      // carry p = 0, so any finite row will do (the tile's own rows, not bytes past it)
+      const int vr0 = 32 * b2 + 4 * g4 + (qi >> 2), vr1 = 2 * b2 + 1 < nbt ? vr0 + 16 : vr0;
       if (tile_fp8) {
         // 8-bit transposed reads: within a lane group, lane qi addresses key slot qi / 2
         // (row 32 b2 + 4 g4 + (qi/2 < 4 ? qi/2 : 16 + qi/2 - 4)) at byte columns

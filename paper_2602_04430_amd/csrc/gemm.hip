@@ -25,7 +25,10 @@ namespace kvop {
 //   0: padded rows (BK + one chunk) — chunk c of row r at r*LDK + c*VEC
 //   1: unpadded, chunk c of row r stored at slot c ^ ((r >> 1) & (CPR-1))
 //   2: unpadded, chunk c of row r stored at slot c ^ (r & (CPR-1))
-template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW>
+// NS = 0: slabs staged through registers (two LDS buffers); NS >= 2: slabs fetched by
+// direct global -> LDS loads into NS buffers, completion tracked with explicit vmcnt waits
+// (every thread issues the same number of loads per slab), K a multiple of BK.
+template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW, int NS>
 __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
                                                       int64_t ldb, int64_t ldc, int tiles_m) {
@@ -41,8 +44,10 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
   auto slot = [](int r, int c) {            // LDS chunk slot of logical chunk c in row r
     if constexpr (SWZ == 1) return c ^ ((r >> 1) & (CPR - 1));
     else if constexpr (SWZ == 2) return c ^ (r & (CPR - 1));
+    else if constexpr (SWZ == 3) return c ^ ((r >> 2) & (CPR - 1));
     else return c;
   };
+  static_assert(NS == 0 || SWZ != 0, "direct loads write unpadded rows");
   static_assert((BM / WM) * (BN / WN) == NW, "one wavefront per sub-tile");
   static_assert(ACH * NT == BM * CPR && BCH * NT == BN * CPR, "tile/thread mismatch");
   static_assert(EPI != EPI_SWIGLU || (NI % 2 == 0), "swiglu needs gate/up block pairs");
@@ -105,13 +110,54 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
     for (int j = 0; j < NI; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int nk = (K + BK - 1) / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  int buf = 0;
   const int lrow = lane & 15, lg = lane >> 4;
+  // direct loads of slab k0 into buffer buf: chunk f = i NT + 64 wave + lane lands at LDS
+  // chunk f (row f / CPR, slot f % CPR) and holds logical chunk slot(row, f % CPR) (the
+  // XOR swizzle is its own inverse); rows past M / N read the last row (never stored)
+  auto dma = [&](int k0, int bf) {
+    T* As = smem + bf * STAGE;
+    T* Bs = As + BM * LDK;
+#pragma unroll
+    for (int i = 0; i < ACH; i++) {
+      const int f = tid + i * NT, r = f / CPR, c = slot(r, f % CPR);
+      const uint8_t* g = reinterpret_cast<const uint8_t*>(
+          A + (int64_t)min(m0 + r, M - 1) * lda + k0 + c * VEC);
+      uint8_t* l = reinterpret_cast<uint8_t*>(As + (i * NT + 64 * wave) * VEC);
+      __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < BCH; i++) {
+      const int f = tid + i * NT, r = f / CPR, c = slot(r, f % CPR);
+      const uint8_t* g = reinterpret_cast<const uint8_t*>(
+          B + (int64_t)min(n0 + r, N - 1) * ldb + k0 + c * VEC);
+      uint8_t* l = reinterpret_cast<uint8_t*>(Bs + (i * NT + 64 * wave) * VEC);
+      __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
+    }
+  };
+  int buf = 0;
+  if constexpr (NS == 0) {
+    gload(0);
+    sstore(0);
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int s = 0; s < NS - 1; s++)
+      if (s < nk) dma(s * BK, s);
+  }
   for (int kt = 0; kt < nk; kt++) {
-    if (kt + 1 < nk) gload((kt + 1) * BK);
+    if constexpr (NS == 0) {
+      if (kt + 1 < nk) gload((kt + 1) * BK);
+    } else {
+      // slab kt has landed once only the later slabs' loads (NS - 2 of them) are in flight
+      constexpr int OPS = ACH + BCH;
+      constexpr int W = (NS - 2) * OPS;
+      static_assert(W <= 63, "vmcnt range");
+      if (kt + NS - 2 < nk) __builtin_amdgcn_s_waitcnt((W & 15) | ((W >> 4) << 14) | (7 << 4) | (15 << 8));
+      else __builtin_amdgcn_s_waitcnt((7 << 4) | (15 << 8));
+      __builtin_amdgcn_s_barrier();  // all loads of slab kt visible; slab kt - 1 consumed
+      buf = kt % NS;
+      if (kt + NS - 1 < nk) dma((kt + NS - 1) * BK, (kt + NS - 1) % NS);
+    }
     const T* As = smem + buf * STAGE + (wm * WM) * LDK;
     const T* Bs = smem + buf * STAGE + BM * LDK + (wn * WN) * LDK;
 #pragma unroll
@@ -139,10 +185,13 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
             acc[i][j] = mfma_bf16(__builtin_bit_cast(u16x8, af[i]), __builtin_bit_cast(u16x8, bfr[j]), acc[i][j]);
       }
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+    if constexpr (NS == 0) {
+      if (kt + 1 < nk) sstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
+  if constexpr (NS != 0) __syncthreads();  // every wavefront is done with the slabs (LDS reused below)
 
   // ---- epilogue.  Lane holds C[row0 + 4*(lane/16) + r][col0 + 16*j + lane%16].  Output
   // columns of one 16-row slab are first formed in registers (SwiGLU pairs gate block j with
@@ -157,7 +206,8 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
   constexpr int LPR = OW / VW;                              // lanes per row
   constexpr int RPP = 64 / LPR;                             // rows per pass
   static_assert(64 % LPR == 0 && 16 % RPP == 0, "epilogue lane split");
-  static_assert(NW * 16 * EP * 4 <= 2 * (BM + BN) * LDK * (int)sizeof(T), "epilogue staging fits the slab buffers");
+  static_assert(NW * 16 * EP * 4 <= (NS == 0 ? 2 : NS) * (BM + BN) * LDK * (int)sizeof(T),
+                "epilogue staging fits the slab buffers");
   const int n_out = EPI == EPI_SWIGLU ? N / 2 : N;
   const int col0 = (EPI == EPI_SWIGLU ? (n0 + wn * WN) / 2 : n0 + wn * WN);
   float* E = reinterpret_cast<float*>(smem_raw) + wave * 16 * EP;
@@ -212,35 +262,39 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
 
 // ------------------------------------------------------------------ tile table
 struct TileCfg {
-  int BM, BN, BK, WM, WN, SWZ, NW;
+  int BM, BN, BK, WM, WN, SWZ, NW, NS;
   const char* name;
 };
 static const TileCfg kF32Tiles[] = {
-    {128, 128, 32, 64, 64, 0, 4, "f32_128x128x32_w64x64"},
-    {64, 128, 32, 32, 64, 0, 4, "f32_64x128x32_w32x64"},
-    {128, 64, 32, 64, 32, 0, 4, "f32_128x64x32_w64x32"},
-    {128, 128, 32, 64, 64, 1, 4, "f32_128x128x32_w64x64_swz1"},
+    {128, 128, 32, 64, 64, 0, 4, 0, "f32_128x128x32_w64x64"},
+    {64, 128, 32, 32, 64, 0, 4, 0, "f32_64x128x32_w32x64"},
+    {128, 64, 32, 64, 32, 0, 4, 0, "f32_128x64x32_w64x32"},
+    {128, 128, 32, 64, 64, 1, 4, 0, "f32_128x128x32_w64x64_swz1"},
 };
 static const TileCfg kBf16Tiles[] = {
-    {128, 128, 64, 64, 64, 0, 4, "bf16_128x128x64_w64x64"},
-    {256, 128, 64, 128, 64, 0, 4, "bf16_256x128x64_w128x64"},
-    {128, 256, 64, 64, 128, 0, 4, "bf16_128x256x64_w64x128"},
-    {64, 128, 64, 32, 64, 0, 4, "bf16_64x128x64_w32x64"},
-    {256, 256, 64, 128, 128, 0, 4, "bf16_256x256x64_w128x128"},
-    {256, 256, 32, 128, 128, 0, 4, "bf16_256x256x32_w128x128"},
-    {128, 128, 64, 64, 64, 1, 4, "bf16_128x128x64_w64x64_swz1"},
-    {128, 128, 64, 64, 64, 2, 4, "bf16_128x128x64_w64x64_swz2"},
-    {256, 256, 64, 128, 128, 1, 4, "bf16_256x256x64_w128x128_swz1"},
-    {256, 128, 64, 128, 64, 1, 4, "bf16_256x128x64_w128x64_swz1"},
-    {256, 256, 64, 128, 64, 1, 8, "bf16_256x256x64_8w_w128x64_swz1"},
-    {256, 256, 64, 64, 128, 1, 8, "bf16_256x256x64_8w_w64x128_swz1"},
-    {256, 256, 64, 128, 64, 2, 8, "bf16_256x256x64_8w_w128x64_swz2"},
-    {256, 256, 64, 128, 64, 0, 8, "bf16_256x256x64_8w_w128x64"},
-    {256, 128, 64, 64, 64, 1, 8, "bf16_256x128x64_8w_w64x64_swz1"},
-    {128, 256, 64, 64, 64, 1, 8, "bf16_128x256x64_8w_w64x64_swz1"},
+    {128, 128, 64, 64, 64, 0, 4, 0, "bf16_128x128x64_w64x64"},
+    {256, 128, 64, 128, 64, 0, 4, 0, "bf16_256x128x64_w128x64"},
+    {128, 256, 64, 64, 128, 0, 4, 0, "bf16_128x256x64_w64x128"},
+    {64, 128, 64, 32, 64, 0, 4, 0, "bf16_64x128x64_w32x64"},
+    {256, 256, 64, 128, 128, 0, 4, 0, "bf16_256x256x64_w128x128"},
+    {256, 256, 32, 128, 128, 0, 4, 0, "bf16_256x256x32_w128x128"},
+    {128, 128, 64, 64, 64, 1, 4, 0, "bf16_128x128x64_w64x64_swz1"},
+    {128, 128, 64, 64, 64, 2, 4, 0, "bf16_128x128x64_w64x64_swz2"},
+    {256, 256, 64, 128, 128, 1, 4, 0, "bf16_256x256x64_w128x128_swz1"},
+    {256, 128, 64, 128, 64, 1, 4, 0, "bf16_256x128x64_w128x64_swz1"},
+    {256, 256, 64, 128, 64, 1, 8, 0, "bf16_256x256x64_8w_w128x64_swz1"},
+    {256, 256, 64, 64, 128, 1, 8, 0, "bf16_256x256x64_8w_w64x128_swz1"},
+    {256, 256, 64, 128, 64, 2, 8, 0, "bf16_256x256x64_8w_w128x64_swz2"},
+    {256, 256, 64, 128, 64, 0, 8, 0, "bf16_256x256x64_8w_w128x64"},
+    {256, 128, 64, 64, 64, 1, 8, 0, "bf16_256x128x64_8w_w64x64_swz1"},
+    {128, 256, 64, 64, 64, 1, 8, 0, "bf16_128x256x64_8w_w64x64_swz1"},
+    {256, 256, 64, 64, 128, 1, 8, 2, "bf16_256x256x64_8w_w64x128_swz1_lds2"},
+    {256, 256, 32, 64, 128, 3, 8, 3, "bf16_256x256x32_8w_w64x128_swz3_lds3"},
+    {256, 256, 32, 64, 128, 3, 8, 4, "bf16_256x256x32_8w_w64x128_swz3_lds4"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 16; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 20; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -251,14 +305,15 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
   int vec = dt == DT_F32 ? 4 : 8;
   if (s.K % vec || s.lda % vec || s.ldb % vec) return false;
   if (epi == EPI_SWIGLU && (s.N % 32 || (c.WN % 32))) return false;
+  if (c.NS && s.K % c.BK) return false;   // direct-load tiles read whole slabs only
   return true;
 }
 
-template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4>
+template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
-  size_t lds = 2 * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW>;
+  size_t lds = (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -296,7 +351,11 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 12: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 2, 8>(A, B, C, s, st);
       case 13: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 0, 8>(A, B, C, s, st);
       case 14: return launch_t<T, TO, EPI, 256, 128, 64, 64, 64, 1, 8>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 128, 256, 64, 64, 64, 1, 8>(A, B, C, s, st);
+      case 15: return launch_t<T, TO, EPI, 128, 256, 64, 64, 64, 1, 8>(A, B, C, s, st);
+      case 16: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8, 2>(A, B, C, s, st);
+      case 17: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 3>(A, B, C, s, st);
+      case 18: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 4>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2>(A, B, C, s, st);
     }
   }
 }

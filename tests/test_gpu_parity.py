@@ -49,7 +49,12 @@ def test_gemm_every_tile_matches_float64(device, dtype, epi):
             out_f32 = dtype == "f32" or epi == 1
             Cd = C0.clone().to(device) if out_f32 else _bf16(C0).to(device)
             ldc = ref.shape[1]
-            K.kvop_debug_gemm(dt, K.KVOP_F32 if out_f32 else K.KVOP_BF16, epi, tile, Ad, Bd, Cd, M, N, Kd, Kd, Kd, ldc)
+            try:
+                K.kvop_debug_gemm(dt, K.KVOP_F32 if out_f32 else K.KVOP_BF16, epi, tile, Ad, Bd, Cd, M, N, Kd, Kd, Kd,
+                                  ldc)
+            except K.KvopError as e:        # direct-load tiles read whole K slabs only
+                assert "lds" in K.kvop_gemm_tile_name(dt, tile) and Kd % 32 != 0 or Kd % 64 != 0, (tile, e)
+                continue
             torch.cuda.synchronize()
             got = Cd.float().cpu().double()
             scale = max(1.0, float(ref.abs().max()))
