@@ -250,6 +250,7 @@ def main():
         "roofline": roofline,
         "roofline_attention": roof_att,
         "kernel_ms_per_step": {k: round(v[0], 3) for k, v in prof.items()},
+        "attention_kernel": K.kvop_get_attention_kernel(),
         "gemm_tiles": tune_report,
         "bf16_plain_tuples_per_s": plain_value,
         "proxy": cascade,

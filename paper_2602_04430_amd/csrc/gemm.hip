@@ -415,6 +415,7 @@ int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
   if (s.M <= 128) return 3;        // 64x128
   if (s.M < 8192) return 7;        // 128x128, 4 wavefronts
+  if (gemm_tile_ok(dt, 19, s, epi)) return 19;  // 256x256, 8 wavefronts of 128x64, direct loads
   return 11;                       // 256x256, 8 wavefronts of 64x128
 }
 

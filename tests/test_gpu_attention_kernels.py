@@ -22,7 +22,7 @@ SHAPE64 = synth.ModelShape(n_layers=2, d_model=256, n_heads=4, n_kv_heads=2, hea
 def attention_kernel():
     """Sets the process-wide attention kernel for one test and restores the default."""
     yield K.kvop_set_attention_kernel
-    K.kvop_set_attention_kernel(-1)
+    K.kvop_set_attention_kernel(0)
 
 
 def _run_filter(shape, w, docs, suffix, kv, variant, set_kernel, rs):
