@@ -127,7 +127,7 @@ def main():
     if args.tuning:
         with open(args.tuning) as f:
             K.kvop_tuning_import(f.read())
-        tune_report = {"imported": args.tuning}
+        tune_report = {"imported": os.path.basename(args.tuning)}
     else:
         tune_report = autotune(K, mb, [n * 32, 60000, n], "bf16")
     proxy = None
@@ -157,6 +157,7 @@ def main():
     K.kvop_profile_start()
     timed_eval(pool, 1.0, hb, steps=1)
     prof = K.kvop_profile_stop()
+    gu_launches = K.kvop_profile_launches("gemm_gate_up")
     log("profile (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in prof.items()})
     cascade = None
     if proxy is not None:
@@ -221,13 +222,17 @@ def main():
                               None if fp32 is None else fp32["logits"])
 
     # ------------------------------------------------------------------ roofline of the dominant kernel
-    gu_ms, gu_cnt = prof["gemm_gate_up"]
+    # the gate/up launches of layers 0..14 run all n * 32 suffix rows; the last layer's runs n rows
+    gu_big = gu_launches[:shape.n_layers - 1]
     rows_main = n * 32
-    gu_flops = 2.0 * shape.d_model * 2 * shape.d_ffn * (rows_main * (shape.n_layers - 1) + n)
+    gu_ms = sum(gu_big) / len(gu_big)
+    gu_flops = 2.0 * shape.d_model * 2 * shape.d_ffn * rows_main
     achieved = gu_flops / (gu_ms / 1e3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "gemm_gate_up (bf16, SwiGLU epilogue)", "achieved": achieved,
-                "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                "launches": gu_cnt, "avg_launch_ms": gu_ms / max(1, gu_cnt)}
+    traffic = counted_traffic(tune_report.get("bf16/gate_up/M=%d" % rows_main))
+    roofline = {"bound": "mfma", "kernel": "gemm_gate_up (bf16, SwiGLU epilogue, M=%d N=%d K=%d)"
+                % (rows_main, 2 * shape.d_ffn, shape.d_model), "achieved": achieved,
+                "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
+                "launches": len(gu_big), "avg_launch_ms": gu_ms, "flops_per_launch": gu_flops}
     att_ms, att_cnt = prof["attention"]
     k1 = int(docs.lengths.sum())
     att_bytes = (k1 + 32 * n) * 2 * shape.n_kv_heads * shape.head_dim * 2 * shape.n_layers
@@ -606,6 +611,23 @@ def time_cascade(K, px, info, pool, handles, pooled, lists, op, full_out, n, arg
     log(f"cascade: {out['tuples_per_s']:.0f} tuples/s, coverage {out['coverage']:.3f}, "
         f"disagreement {out['disagreement_vs_full_operator']:.4f}")
     return out
+
+
+def counted_traffic(tile):
+    """HBM bytes per gate/up launch from the committed rocprofv3 counter summary, or None when
+    the GEMM source or the tile differs from the one the counters were taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "gemm_gate_up_bf16_filter4096_hbm.md")
+    src = os.path.join(here, "paper_2602_04430_amd", "csrc", "gemm.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "gemm_hip_sha256", "tile"))
+        same_src = hashlib.sha256(open(src, "rb").read()).hexdigest() == fields["gemm_hip_sha256"].strip()
+        same_tile = tile is None or tile == fields.get("tile", tile).strip()
+        return float(fields["traffic_bytes_per_launch"]) if same_src and same_tile else None
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def copy_probe(dev):

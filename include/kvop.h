@@ -260,6 +260,9 @@ kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epilogue, 
  * milliseconds and the number of launches (classes named by kvop_profile_class_name). */
 kvop_status kvop_profile_start(void);
 kvop_status kvop_profile_stop(double* ms_out, int64_t* count_out, int32_t n);
+/* Per-launch milliseconds of class cls from the last start/stop interval, in launch order:
+ * writes min(n, count) values to ms_out (nullable) and returns the count (-1: bad class). */
+int32_t kvop_profile_launches(int32_t cls, double* ms_out, int32_t n);
 int32_t kvop_profile_num_classes(void);
 const char* kvop_profile_class_name(int32_t i);
 /* Autotuner: for each projection of the model (QKV, O, gate/up, down) at M = rows, time

@@ -39,6 +39,7 @@ struct Prof {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   double ms[PC_COUNT] = {};
   int64_t cnt[PC_COUNT] = {};
+  std::vector<double> launches[PC_COUNT];  // per-launch milliseconds, in launch order
   hipEvent_t get() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
     hipEvent_t e = nullptr;
@@ -1575,7 +1576,7 @@ kvop_status kvop_set_wave_rows(int64_t rows) {
 // ------------------------------------------------------------------ profiling
 kvop_status kvop_profile_start(void) {
   g_prof.on = true;
-  for (int i = 0; i < PC_COUNT; i++) { g_prof.ms[i] = 0; g_prof.cnt[i] = 0; }
+  for (int i = 0; i < PC_COUNT; i++) { g_prof.ms[i] = 0; g_prof.cnt[i] = 0; g_prof.launches[i].clear(); }
   for (auto& pe : g_prof.pending) { g_prof.pool.push_back(pe.second.first); g_prof.pool.push_back(pe.second.second); }
   g_prof.pending.clear();
   return KVOP_OK;
@@ -1589,6 +1590,7 @@ kvop_status kvop_profile_stop(double* ms_out, int64_t* count_out, int32_t n) {
     HIPTRY(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
     g_prof.ms[pe.first] += ms;
     g_prof.cnt[pe.first] += 1;
+    g_prof.launches[pe.first].push_back(ms);
     g_prof.pool.push_back(pe.second.first);
     g_prof.pool.push_back(pe.second.second);
   }
@@ -1598,6 +1600,13 @@ kvop_status kvop_profile_stop(double* ms_out, int64_t* count_out, int32_t n) {
     if (count_out) count_out[i] = g_prof.cnt[i];
   }
   return KVOP_OK;
+}
+
+int32_t kvop_profile_launches(int32_t cls, double* ms_out, int32_t n) {
+  if (cls < 0 || cls >= PC_COUNT) return -1;
+  const auto& v = g_prof.launches[cls];
+  for (int32_t i = 0; i < n && i < (int32_t)v.size(); i++) if (ms_out) ms_out[i] = v[i];
+  return (int32_t)v.size();
 }
 
 int32_t kvop_profile_num_classes(void) { return PC_COUNT; }

@@ -89,6 +89,7 @@ _SIGS = {
     "kvop_profile_start": (C.c_int, []),
     "kvop_profile_stop": (C.c_int, [_P, _P, C.c_int32]),
     "kvop_profile_num_classes": (C.c_int32, []),
+    "kvop_profile_launches": (C.c_int32, [C.c_int32, _P, C.c_int32]),
     "kvop_profile_class_name": (C.c_char_p, [C.c_int32]),
 }
 _lib_handle = None
@@ -239,6 +240,16 @@ def kvop_profile_stop() -> dict:
     cnt = np.zeros(n, np.int64)
     _check(lib().kvop_profile_stop(ms.ctypes.data_as(C.c_void_p), cnt.ctypes.data_as(C.c_void_p), n))
     return {lib().kvop_profile_class_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def kvop_profile_launches(name: str) -> list:
+    """Per-launch milliseconds of one class since the last kvop_profile_start/stop."""
+    names = [lib().kvop_profile_class_name(i).decode() for i in range(kvop_profile_num_classes())]
+    cls = names.index(name)
+    n = int(lib().kvop_profile_launches(cls, None, 0))
+    out = np.zeros(max(n, 1), np.float64)
+    lib().kvop_profile_launches(cls, out.ctypes.data_as(C.c_void_p), n)
+    return out[:n].tolist()
 
 
 def kvop_profile_num_classes() -> int:
