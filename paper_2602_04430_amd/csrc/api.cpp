@@ -948,7 +948,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     int32_t* tk = tokens_out;
     const int32_t* orow = (const int32_t*)(md + o_out);
     HIPTRY(head_map(m->dt, xlast, (int64_t)S * d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, nullptr, orow, lg,
-                    (int64_t)n_gen * ln, tk, n_gen, ntok, st));
+                    (int64_t)n_gen * ln, tk, n_gen, ntok, false, st));
     for (int t = 1; t < n_gen; t++) {
         ProfScope decode_scope(PC_DECODE, st);
       // positions of the fed token: L + S + t - 1; it is own row S + t - 1 of its item
@@ -1029,7 +1029,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
         }
       }
       HIPTRY(head_map(m->dt, bufs.x, d, B, d, m->final_norm, c.rms_eps, m->head, op->label_lo, ln, nullptr, orow,
-                      lg + (int64_t)t * ln, (int64_t)n_gen * ln, tk + t, n_gen, ntok, st));
+                      lg + (int64_t)t * ln, (int64_t)n_gen * ln, tk + t, n_gen, ntok, false, st));
     }
   }
   return KVOP_OK;
@@ -1146,6 +1146,28 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
   const bool use_graph = (flags & KVOP_MIXED_GRAPH) != 0;
   const bool persistent = (flags & KVOP_MIXED_PERSISTENT) != 0;
   int* counter = m->dflag + 16;
+  int Pmax = 64;
+  for (int k = 0; k < n_ops; k++) Pmax = std::min(Pmax, std::max(1, std::min(ops[k].op.suffix_len, 64 / G)));
+  // map decoding runs once after all waves, over every map item of the call: each wave
+  // stores its map items' suffix keys/values (all layers) and first token; the decode
+  // steps then run with all map items as rows
+  const int nm_all = map_op >= 0 ? (int)by_op[map_op].size() : 0;
+  const int n_gen = map_op >= 0 ? ops[map_op].op.n_gen : 1;
+  const int Sm = map_op >= 0 ? ops[map_op].op.suffix_len : 0;
+  const int rpi = Sm + n_gen - 1;  // own rows per map item: suffix + generated
+  int64_t wave_rows_max = 0;
+  for (int k = 0; k < n_ops; k++) wave_rows_max += (int64_t)per[k] * ops[k].op.suffix_len;
+  const size_t act_w = align_up(act_bytes(m, wave_rows_max, any_join), kAlign);
+  const size_t own_layer = (size_t)nm_all * rpi * own_ld * e;       // one layer's own rows of all map items
+  const size_t own_all = align_up((size_t)c.n_layers * own_layer, kAlign);
+  const size_t ntok_bytes = align_up((size_t)std::max(nm_all, 1) * 4, kAlign);
+  const size_t act_d = nm_all > 0 ? align_up(act_bytes(m, nm_all, false), kAlign) : 0;
+  if (m->ws.reserve(act_w + own_all + ntok_bytes + act_d, st) != hipSuccess)
+    return fail(KVOP_ENOMEM, "activation workspace");
+  char* ws = (char*)m->ws.p;
+  LayerBufs bufs = carve(m, ws, wave_rows_max, any_join);
+  char* ownbuf = ws + act_w;
+  int32_t* ntok_all = (int32_t*)(ws + act_w + own_all);
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   auto cleanup_graph = [&]() {
@@ -1173,8 +1195,6 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     std::vector<int32_t> tok(rows), pos(rows), shift(any_join ? rows : 0, -1);
     std::vector<AttnWork> work;
     std::vector<std::vector<int32_t>> in_rows(n_ops), out_rows(n_ops);
-    int Pmax = 64;
-    for (int k = 0; k < n_ops; k++) Pmax = std::min(Pmax, std::max(1, std::min(ops[k].op.suffix_len, 64 / G)));
     for (int k = 0; k < n_ops; k++) {
       const kvop_op& o = ops[k].op;
       const int S = o.suffix_len;
@@ -1219,42 +1239,15 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     }
     std::stable_sort(work.begin(), work.end(),
                      [](const AttnWork& a, const AttnWork& b) { return a.n_a + a.n_b > b.n_a + b.n_b; });
-    // map decode metadata for every step
+    // map items of this wave: suffix rows -> own rows of their call-wide index (= output row)
     const int nm = map_op >= 0 ? blk_n[map_op] : 0;
-    const int n_gen = map_op >= 0 ? ops[map_op].op.n_gen : 1;
-    const int Sm = map_op >= 0 ? ops[map_op].op.suffix_len : 0;
-    const int rpi = Sm + n_gen - 1;
-    std::vector<int32_t> own_src, own_dst, dec_src, pdec, ddst;
-    std::vector<AttnWork> dwork;
-    if (nm > 0) {
-      for (int b = 0; b < nm; b++) {
-        dec_src.push_back(b);
-        for (int j = 0; j < Sm; j++) {
-          own_src.push_back(blk_row[map_op] + b * Sm + j);
-          own_dst.push_back(b * rpi + j);
-        }
+    std::vector<int32_t> own_src, own_dst;
+    for (int b = 0; b < nm; b++) {
+      const int g = rank[item_at(map_op, b)];
+      for (int j = 0; j < Sm; j++) {
+        own_src.push_back(blk_row[map_op] + b * Sm + j);
+        own_dst.push_back(g * rpi + j);
       }
-      for (int t = 1; t < n_gen; t++)
-        for (int b = 0; b < nm; b++) {
-          const int it = item_at(map_op, b);
-          const DocSlot* A = docA[it];
-          pdec.push_back(A->L + Sm + t - 1);
-          ddst.push_back(b * rpi + Sm + t - 1);
-          AttnWork wk{};
-          wk.off_a = (int64_t)A->off;
-          wk.off_b = -1;
-          wk.idx_a = idx_off[item_list[it]];
-          wk.idx_b = -1;
-          wk.L_a = A->L;
-          wk.n_a = (int32_t)(idx_off[item_list[it] + 1] - idx_off[item_list[it]]);
-          wk.q_row0 = b;
-          wk.q_pos0 = A->L + Sm + t - 1;
-          wk.n_q = 1;
-          wk.own_row0 = b * rpi;
-          wk.n_own = Sm + t;
-          wk.own_pos0 = A->L;
-          dwork.push_back(wk);
-        }
     }
     // ---- metadata layout (identical for every full wave)
     Mirror mir;
@@ -1265,11 +1258,11 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
       o_in[k] = mir.add(in_rows[k].size() * 4);
       o_out[k] = mir.add(out_rows[k].size() * 4);
     }
-    const size_t o_os = mir.add(own_src.size() * 4), o_od = mir.add(own_dst.size() * 4),
-                 o_ds = mir.add(dec_src.size() * 4), o_pd = mir.add(pdec.size() * 4), o_dd = mir.add(ddst.size() * 4),
-                 o_dw = mir.add(dwork.size() * sizeof(AttnWork)), o_ntok = mir.add(nm * 4);
-    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+    const size_t o_os = mir.add(own_src.size() * 4), o_od = mir.add(own_dst.size() * 4);
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess) {
+      cleanup_graph();
       return fail(KVOP_ENOMEM, "metadata staging");
+    }
     char* hp = m->stage.p;
     auto put = [&](size_t o, const void* src, size_t n) { if (n) memcpy(hp + o, src, n); };
     put(o_tok, tok.data(), rows * 4);
@@ -1282,19 +1275,14 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     }
     put(o_os, own_src.data(), own_src.size() * 4);
     put(o_od, own_dst.data(), own_dst.size() * 4);
-    put(o_ds, dec_src.data(), dec_src.size() * 4);
-    put(o_pd, pdec.data(), pdec.size() * 4);
-    put(o_dd, ddst.data(), ddst.size() * 4);
-    put(o_dw, dwork.data(), dwork.size() * sizeof(AttnWork));
-    const size_t act = act_bytes(m, rows, any_join);
-    const size_t own_bytes = (size_t)c.n_layers * nm * rpi * own_ld * e;
-    if (m->ws.reserve(act + align_up(own_bytes, kAlign), st) != hipSuccess) return fail(KVOP_ENOMEM, "activation workspace");
     char* md = (char*)m->meta.p;
-    HIPTRY(hipMemcpyAsync(md, hp, o_ntok, hipMemcpyHostToDevice, st));
-    HIPTRY(hipEventRecord(m->stage.ev, st));
+    if (hipMemcpyAsync(md, hp, mir.size, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipEventRecord(m->stage.ev, st) != hipSuccess) {
+      (void)hipGetLastError();
+      cleanup_graph();
+      return fail(KVOP_EDEVICE, "metadata upload");
+    }
     m->stage.pending = true;
-    LayerBufs bufs = carve(m, (char*)m->ws.p, rows, any_join);
-    char* ownbuf = (char*)m->ws.p + act;
 
     // ---- the wave's launch sequence (enqueued directly, or captured once and replayed)
     auto enqueue = [&](hipStream_t st) -> kvop_status {
@@ -1326,81 +1314,21 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
         if (s != KVOP_OK) return s;
         if (nm > 0)
           HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_os),
-                              (const int32_t*)(md + o_od), nm * Sm, ownbuf + (size_t)l * nm * rpi * own_ld * e, own_ld,
-                              st));
+                              (const int32_t*)(md + o_od), nm * Sm, ownbuf + (size_t)l * own_layer, own_ld, st));
       }
       for (int k = 0; k < n_ops; k++) {
         const kvop_op& o = ops[k].op;
-        if (o.kind == KVOP_MAP || blk_n[k] == 0) continue;
+        if (blk_n[k] == 0) continue;
+        if (o.kind == KVOP_MAP) {
+          // first generated id of every map item: logits, token and the next input at its row
+          HIPTRY(head_map(m->dt, bufs.x, d, blk_n[k], d, m->final_norm, c.rms_eps, m->head, o.label_lo, o.label_n,
+                          (const int32_t*)(md + o_in[k]), (const int32_t*)(md + o_out[k]), ops[k].logits_out_dev,
+                          (int64_t)o.n_gen * o.label_n, ops[k].tokens_out_dev, o.n_gen, ntok_all, true, st));
+          continue;
+        }
         HIPTRY(head_filter(m->dt, bufs.x, d, blk_n[k], d, m->final_norm, c.rms_eps, m->head, o.yes_id, o.no_id,
                            o.theta_pos, o.theta_neg, (const int32_t*)(md + o_in[k]), (const int32_t*)(md + o_out[k]),
                            ops[k].logits_out_dev, ops[k].decision_out_dev, st));
-      }
-      if (nm == 0) return KVOP_OK;
-      const kvop_op& o = ops[map_op].op;
-      const int ln = o.label_n;
-      int32_t* ntok = (int32_t*)(md + o_ntok);
-      const int32_t* orow = (const int32_t*)(md + o_out[map_op]);
-      HIPTRY(head_map(m->dt, bufs.x, d, nm, d, m->final_norm, c.rms_eps, m->head, o.label_lo, ln,
-                      (const int32_t*)(md + o_in[map_op]), orow, ops[map_op].logits_out_dev, (int64_t)n_gen * ln,
-                      ops[map_op].tokens_out_dev, n_gen, ntok, st));
-      for (int t = 1; t < n_gen; t++) {
-        ProfScope decode_scope(PC_DECODE, st);
-        const int32_t* pd = (const int32_t*)(md + o_pd) + (size_t)(t - 1) * nm;
-        const int32_t* dd = (const int32_t*)(md + o_dd) + (size_t)(t - 1) * nm;
-        const AttnWork* dw = (const AttnWork*)(md + o_dw) + (size_t)(t - 1) * nm;
-        HIPTRY(embed_rows(m->dt, m->embed, ntok, nm, d, c.vocab, bufs.x, st));
-        for (int l = 0; l < c.n_layers; l++) {
-          char* own_l = ownbuf + (size_t)l * nm * rpi * own_ld * e;
-          const kvop_model::Layer& Wl = m->layers[l];
-          HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, Wl.attn_norm, nm, d, c.rms_eps, bufs.h, d, st));
-          {
-            GemmShape g{nm, qc, d, d, d, qc};
-            HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, g), bufs.h, Wl.wqkv, bufs.qkv, g, st));
-          }
-          HIPTRY(rope_qk(m->dt, bufs.qkv, qc, nm, H, Hkv, D, pd, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
-          HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_ds), dd, nm, own_l,
-                              own_ld, st));
-          AttnArgs a{};
-          a.work = dw;
-          a.n_work = nm;
-          a.idx = idx;
-          a.pool = p->base;
-          a.q = bufs.qkv;
-          a.q_stride = qc;
-          a.own = own_l;
-          a.own_stride = own_ld;
-          a.own_kcol = 0;
-          a.own_vcol = Hkv * D;
-          a.out = bufs.attn;
-          a.out_stride = H * D;
-          a.layer = l;
-          a.n_layers = c.n_layers;
-          a.Hkv = Hkv;
-          a.G = G;
-          a.Pmax = 1;
-          a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
-          a.counter = persistent ? counter : nullptr;
-          a.persistent_wgs = 2 * m->n_cu;
-          if (a.counter) HIPTRY(fill_i32(a.counter, 0, 1, st));
-          HIPTRY(attention(m->dt, p->kvdt, D, a, st));
-          {
-            GemmShape g{nm, d, H * D, H * D, H * D, d};
-            HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, g), bufs.attn, Wl.wo, bufs.x, g, st));
-          }
-          HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, Wl.ffn_norm, nm, d, c.rms_eps, bufs.h, d, st));
-          {
-            GemmShape g{nm, 2 * F, d, d, d, F};
-            HIPTRY(gemm(m->dt, m->dt, EPI_SWIGLU, gemm_pick_tile(m->dt, EPI_SWIGLU, g), bufs.h, Wl.wgu, bufs.act, g, st));
-          }
-          {
-            GemmShape g{nm, d, F, F, F, d};
-            HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, g), bufs.act, Wl.wdown, bufs.x, g, st));
-          }
-        }
-        HIPTRY(head_map(m->dt, bufs.x, d, nm, d, m->final_norm, c.rms_eps, m->head, o.label_lo, ln, nullptr, orow,
-                        ops[map_op].logits_out_dev + (int64_t)t * ln, (int64_t)n_gen * ln, ops[map_op].tokens_out_dev + t,
-                        n_gen, ntok, st));
       }
       return KVOP_OK;
     };
@@ -1454,6 +1382,109 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     if (hipStreamSynchronize(st) != hipSuccess) { cleanup_graph(); return fail(KVOP_EDEVICE, "graph replay failed"); }
   }
   cleanup_graph();
+  if (nm_all == 0 || n_gen < 2) return KVOP_OK;
+
+  // ---- map decoding over all map items of the call (rows g = call-wide map index)
+  {
+    const kvop_op& o = ops[map_op].op;
+    const int ln = o.label_n;
+    std::vector<int32_t> ident(nm_all), pdec, ddst;
+    std::vector<AttnWork> dwork;
+    for (int g = 0; g < nm_all; g++) ident[g] = g;
+    for (int t = 1; t < n_gen; t++)
+      for (int g = 0; g < nm_all; g++) {
+        const int it = by_op[map_op][g];
+        const DocSlot* A = docA[it];
+        pdec.push_back(A->L + Sm + t - 1);
+        ddst.push_back(g * rpi + Sm + t - 1);
+        AttnWork wk{};
+        wk.off_a = (int64_t)A->off;
+        wk.off_b = -1;
+        wk.idx_a = idx_off[item_list[it]];
+        wk.idx_b = -1;
+        wk.L_a = A->L;
+        wk.n_a = (int32_t)(idx_off[item_list[it] + 1] - idx_off[item_list[it]]);
+        wk.q_row0 = g;
+        wk.q_pos0 = A->L + Sm + t - 1;
+        wk.n_q = 1;
+        wk.own_row0 = g * rpi;
+        wk.n_own = Sm + t;
+        wk.own_pos0 = A->L;
+        dwork.push_back(wk);
+      }
+    Mirror mir;
+    const size_t o_id = mir.add(ident.size() * 4), o_pd = mir.add(pdec.size() * 4), o_dd = mir.add(ddst.size() * 4),
+                 o_dw = mir.add(dwork.size() * sizeof(AttnWork));
+    if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+      return fail(KVOP_ENOMEM, "metadata staging");
+    memcpy(m->stage.p + o_id, ident.data(), ident.size() * 4);
+    memcpy(m->stage.p + o_pd, pdec.data(), pdec.size() * 4);
+    memcpy(m->stage.p + o_dd, ddst.data(), ddst.size() * 4);
+    memcpy(m->stage.p + o_dw, dwork.data(), dwork.size() * sizeof(AttnWork));
+    char* md = (char*)m->meta.p;
+    HIPTRY(hipMemcpyAsync(md, m->stage.p, mir.size, hipMemcpyHostToDevice, st));
+    HIPTRY(hipEventRecord(m->stage.ev, st));
+    m->stage.pending = true;
+    LayerBufs db = carve(m, ws + act_w + own_all + ntok_bytes, nm_all, false);
+    const int32_t* id = (const int32_t*)(md + o_id);
+    for (int t = 1; t < n_gen; t++) {
+      ProfScope decode_scope(PC_DECODE, st);
+      const int32_t* pd = (const int32_t*)(md + o_pd) + (size_t)(t - 1) * nm_all;
+      const int32_t* dd = (const int32_t*)(md + o_dd) + (size_t)(t - 1) * nm_all;
+      const AttnWork* dw = (const AttnWork*)(md + o_dw) + (size_t)(t - 1) * nm_all;
+      HIPTRY(embed_rows(m->dt, m->embed, ntok_all, nm_all, d, c.vocab, db.x, st));
+      for (int l = 0; l < c.n_layers; l++) {
+        char* own_l = ownbuf + (size_t)l * own_layer;
+        const kvop_model::Layer& Wl = m->layers[l];
+        HIPTRY(rmsnorm_rows(m->dt, db.x, d, Wl.attn_norm, nm_all, d, c.rms_eps, db.h, d, st));
+        {
+          GemmShape g{nm_all, qc, d, d, d, qc};
+          HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, g), db.h, Wl.wqkv, db.qkv, g, st));
+        }
+        HIPTRY(rope_qk(m->dt, db.qkv, qc, nm_all, H, Hkv, D, pd, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
+        HIPTRY(copy_kv_rows(m->dt, db.qkv, qc, H * D, 2 * Hkv * D, id, dd, nm_all, own_l, own_ld, st));
+        AttnArgs a{};
+        a.work = dw;
+        a.n_work = nm_all;
+        a.idx = idx;
+        a.pool = p->base;
+        a.q = db.qkv;
+        a.q_stride = qc;
+        a.own = own_l;
+        a.own_stride = own_ld;
+        a.own_kcol = 0;
+        a.own_vcol = Hkv * D;
+        a.out = db.attn;
+        a.out_stride = H * D;
+        a.layer = l;
+        a.n_layers = c.n_layers;
+        a.Hkv = Hkv;
+        a.G = G;
+        a.Pmax = 1;
+        a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
+        a.counter = persistent ? counter : nullptr;
+        a.persistent_wgs = 2 * m->n_cu;
+        if (a.counter) HIPTRY(fill_i32(a.counter, 0, 1, st));
+        HIPTRY(attention(m->dt, p->kvdt, D, a, st));
+        {
+          GemmShape g{nm_all, d, H * D, H * D, H * D, d};
+          HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, g), db.attn, Wl.wo, db.x, g, st));
+        }
+        HIPTRY(rmsnorm_rows(m->dt, db.x, d, Wl.ffn_norm, nm_all, d, c.rms_eps, db.h, d, st));
+        {
+          GemmShape g{nm_all, 2 * F, d, d, d, F};
+          HIPTRY(gemm(m->dt, m->dt, EPI_SWIGLU, gemm_pick_tile(m->dt, EPI_SWIGLU, g), db.h, Wl.wgu, db.act, g, st));
+        }
+        {
+          GemmShape g{nm_all, d, F, F, F, d};
+          HIPTRY(gemm(m->dt, DT_F32, EPI_ADD, gemm_pick_tile(m->dt, EPI_ADD, g), db.act, Wl.wdown, db.x, g, st));
+        }
+      }
+      HIPTRY(head_map(m->dt, db.x, d, nm_all, d, m->final_norm, c.rms_eps, m->head, o.label_lo, ln, nullptr, id,
+                      ops[map_op].logits_out_dev + (int64_t)t * ln, (int64_t)n_gen * ln, ops[map_op].tokens_out_dev + t,
+                      n_gen, ntok_all, false, st));
+    }
+  }
   return KVOP_OK;
 }
 

@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
                                                        const int32_t* __restrict__ out_rows,
                                                        float* __restrict__ logits, int64_t ldl,
                                                        int32_t* __restrict__ tok_out, int64_t ldt,
-                                                       int32_t* __restrict__ next_tok) {
+                                                       int32_t* __restrict__ next_tok, bool next_by_out) {
   extern __shared__ float ysm[];       // d floats, then n logits
   __shared__ float red[4];
   __shared__ int redi[4];
@@ -386,21 +386,22 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
     for (int k = 1; k < 4; k++)
       if (red[k] > b || (red[k] == b && redi[k] < i)) { b = red[k]; i = redi[k]; }
     tok_out[orow * ldt] = lo + i;
-    if (next_tok) next_tok[item] = lo + i;
+    if (next_tok) next_tok[next_by_out ? orow : item] = lo + i;
   }
 }
 
 hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
                     const void* head, int lo, int n, const int32_t* in_rows, const int32_t* out_rows, float* logits,
-                    int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st) {
+                    int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, bool next_by_out,
+                    hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   size_t lds = (size_t)(d + n) * sizeof(float);
   if (dt == DT_F32)
     hipLaunchKernelGGL(head_map_kernel<float>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps, (const float*)head,
-                       lo, n, in_rows, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
+                       lo, n, in_rows, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok, next_by_out);
   else
     hipLaunchKernelGGL(head_map_kernel<bf16_t>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps,
-                       (const bf16_t*)head, lo, n, in_rows, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok);
+                       (const bf16_t*)head, lo, n, in_rows, out_rows, logits, ld_logits, tok_out, ld_tok, next_tok, next_by_out);
   return hipGetLastError();
 }
 

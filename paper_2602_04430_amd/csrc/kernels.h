@@ -121,10 +121,13 @@ hipError_t pooled_mean(const float* x, int d, const int64_t* row_off, int n_docs
 hipError_t head_filter(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
                        const void* head, int yes_id, int no_id, float th_pos, float th_neg, const int32_t* in_rows,
                        const int32_t* out_rows, float* logits, int8_t* decision, hipStream_t st);
-// map head: logits over [lo, lo+n) and argmax (lowest id on ties)
+// map head: logits over [lo, lo+n) and argmax (lowest id on ties); the argmax id goes to
+// tok_out[out_row * ld_tok] and, when next_tok is set, to next_tok[out_row] (next_by_out) or
+// next_tok[item]
 hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, const float* g, float eps,
                     const void* head, int lo, int n, const int32_t* in_rows, const int32_t* out_rows, float* logits,
-                    int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, hipStream_t st);
+                    int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, bool next_by_out,
+                    hipStream_t st);
 // index-list validation: counts lists that are unsorted or out of range into *bad
 struct ListCheck {
   int64_t off;
