@@ -283,9 +283,9 @@ kvop_status kvop_tuning_import(const char* text);
 kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epilogue, int32_t N, int32_t K, int32_t M, int32_t tile);
 /* Attention kernel used for BF16 compute with a BF16 or FP8 cache and head_dim 64 or 128
  * (all other cases use the register-staged kernel): -1 = register-staged key/value tiles;
- * 0, 1, 2 = tiles fetched by direct global -> LDS loads with 64-key tiles and 2 stages (the
- * default), 64-key tiles and 3 stages, 32-key tiles and 3 stages (head_dim 64 uses 64-key
- * tiles for 2).  Process-wide; EINVAL outside -1 .. 2.  Results agree within the stated
+ * 0, 1, 2 = tiles fetched by direct global -> LDS loads with 64-key tiles and 2 stages,
+ * 64-key tiles and 3 stages, 32-key tiles and 3 stages (the default; head_dim 64 uses
+ * 64-key tiles for 2).  Process-wide; EINVAL outside -1 .. 2.  Results agree within the stated
  * bounds; variants with 64-key tiles give the register-staged kernel's results exactly for
  * a BF16 cache. */
 kvop_status kvop_set_attention_kernel(int32_t variant);

@@ -157,18 +157,19 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
   const int64_t qrow = (int64_t)w.q_row0 + (qvalid ? p : 0);
 
   // ---- query fragments (B operand of S^T); qa: rotated for document B (joins)
-  u32x4 qf[NQ], qa[NQ];
+  // (joins: the fragments of the queries rotated at position - L_A are loaded when the
+  // tiles of document B begin, and the plain ones again after them; holding both sets
+  // would cost the registers of a third resident workgroup)
+  u32x4 qf[NQ];
   const bool has_b = w.n_b > 0;
-  {
-    const bf16_t* q = reinterpret_cast<const bf16_t*>(a.q) + qrow * a.q_stride + hq * D;
-    const bf16_t* q2 = reinterpret_cast<const bf16_t*>(a.q_alt ? a.q_alt : a.q) + qrow * a.q_stride + hq * D;
+  const bf16_t* q_plain = reinterpret_cast<const bf16_t*>(a.q) + qrow * a.q_stride + hq * D;
+  const bf16_t* q_rot = reinterpret_cast<const bf16_t*>(a.q_alt ? a.q_alt : a.q) + qrow * a.q_stride + hq * D;
+  auto load_q = [&](const bf16_t* q) {
 #pragma unroll
-    for (int k = 0; k < NQ; k++) {
-      const int d0 = 32 * k + 8 * g4;
-      qf[k] = qvalid ? *reinterpret_cast<const u32x4*>(q + d0) : u32x4{0, 0, 0, 0};
-      qa[k] = (qvalid && has_b) ? *reinterpret_cast<const u32x4*>(q2 + d0) : u32x4{0, 0, 0, 0};
-    }
-  }
+    for (int k = 0; k < NQ; k++)
+      qf[k] = qvalid ? gload(reinterpret_cast<const u32x4*>(q + 32 * k + 8 * g4)) : u32x4{0, 0, 0, 0};
+  };
+  load_q(q_plain);
 
   // ---- key sources: 0 = document A, 1 = document B, 2 = own rows.  Three separate
   // variables selected field by field (a dynamically indexed local array would live in
@@ -341,14 +342,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
     const int* rows_s = ring + (ti % (NS + 1)) * 64;
 
     // document B is scored with the queries rotated at (position - L_A)
-    if (has_b && (ti == TA || ti == TA + TB)) {
-#pragma unroll
-      for (int k = 0; k < NQ; k++) {
-        const u32x4 tmp = qf[k];
-        qf[k] = qa[k];
-        qa[k] = tmp;
-      }
-    }
+    if (has_b && (ti == TA || ti == TA + TB)) load_q(ti == TA ? q_rot : q_plain);
     if (!wave_active) continue;
 
     // ---- scores S^T[key][query]: lane holds keys 16 b + 4 g4 + t of query column qi
@@ -461,18 +455,27 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
         const int rb = own ? C::RBO : C::RBC;
         const int s0 = own ? swz_v<C::CHO>(vr0) : swz_v<C::CHC>(vr0);
         const int s1 = own ? swz_v<C::CHO>(vr1) : swz_v<C::CHC>(vr1);
-        u32x2 y[2 * ND];
+        // 32-key tiles: in two halves of the d blocks (fewer live registers, for the
+        // register budget of three resident workgroups)
+        constexpr int NHALF = KT == 32 ? 2 : 1;
 #pragma unroll
-        for (int i = 0; i < ND; i++) {
-          const int cch = (16 * i + 4 * (qi & 3)) >> 3, half = qi & 1;
-          y[2 * i] = ds_read_tr16(Vp + vr0 * rb + (cch ^ s0) * 16 + half * 8);
-          y[2 * i + 1] = ds_read_tr16(Vp + vr1 * rb + (cch ^ s1) * 16 + half * 8);
-        }
-        lgkm_wait_all<2 * ND>(y);
+        for (int h2 = 0; h2 < NHALF; h2++) {
+          constexpr int NH = ND / NHALF;
+          u32x2 y[2 * NH];
 #pragma unroll
-        for (int i = 0; i < ND; i++) {
-          const u32x4 va = u32x4{y[2 * i][0], y[2 * i][1], y[2 * i + 1][0], y[2 * i + 1][1]};
-          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
+          for (int ii = 0; ii < NH; ii++) {
+            const int i = h2 * NH + ii;
+            const int cch = (16 * i + 4 * (qi & 3)) >> 3, half = qi & 1;
+            y[2 * ii] = ds_read_tr16(Vp + vr0 * rb + (cch ^ s0) * 16 + half * 8);
+            y[2 * ii + 1] = ds_read_tr16(Vp + vr1 * rb + (cch ^ s1) * 16 + half * 8);
+          }
+          lgkm_wait_all<2 * NH>(y);
+#pragma unroll
+          for (int ii = 0; ii < NH; ii++) {
+            const int i = h2 * NH + ii;
+            const u32x4 va = u32x4{y[2 * ii][0], y[2 * ii][1], y[2 * ii + 1][0], y[2 * ii + 1][1]};
+            o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
+          }
         }
       }
     }
@@ -496,8 +499,10 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
 }
 
 // One workgroup per unit.
+// 32-key tiles fit three workgroups' rings in LDS; the register budget is capped to match
 template <typename TKV, int D, int KT, int NS>
-__global__ __launch_bounds__(256) void attn_dma_kernel(AttnArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KT == 32 ? 3 : 1)))
+void attn_dma_kernel(AttnArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
   attn_dma_unit<TKV, D, KT, NS>(a, blockIdx.x, dma_smem);
 }
@@ -506,7 +511,8 @@ __global__ __launch_bounds__(256) void attn_dma_kernel(AttnArgs a) {
 // before the launch) until every unit is taken; every workgroup exits once the counter
 // passes the unit count, so the grid always drains.
 template <typename TKV, int D, int KT, int NS>
-__global__ __launch_bounds__(256) void attn_dma_persistent_kernel(AttnArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KT == 32 ? 3 : 1)))
+void attn_dma_persistent_kernel(AttnArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
   __shared__ int next;
   const int total = a.n_work * a.Hkv;

@@ -79,38 +79,85 @@ hipError_t rmsnorm_rows(int dt, const float* x, int64_t ldx, const float* g, int
 }
 
 // ---------------------------------------------------------------- rotary embedding
-// thread per (row, head, pair i): (x_i, x_{i+D/2}) -> (x_i c - x_{i+D/2} s, x_{i+D/2} c + x_i s)
-template <typename T>
-__global__ void rope_kernel(T* __restrict__ qkv, int64_t ld, int n_rows, int n_heads, int H, int D,
-                            const int32_t* __restrict__ pos, const float* __restrict__ cos_t,
-                            const float* __restrict__ sin_t, T* __restrict__ q_alt, const int32_t* __restrict__ shift) {
-  const int half = D / 2;
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t per_row = (int64_t)n_heads * half;
-  if (gid >= per_row * n_rows) return;
-  int row = (int)(gid / per_row);
-  int rem = (int)(gid % per_row);
-  int head = rem / half, i = rem % half;
-  T* v = qkv + (int64_t)row * ld + head * D;
-  float x1 = to_f32(v[i]), x2 = to_f32(v[i + half]);
-  int p = pos[row];
-  float c = cos_t[(int64_t)p * half + i], s = sin_t[(int64_t)p * half + i];
-  if (q_alt && head < H && shift[row] >= 0) {
-    int p2 = p - shift[row];
-    float c2 = cos_t[(int64_t)p2 * half + i], s2 = sin_t[(int64_t)p2 * half + i];
-    T* va = q_alt + (int64_t)row * ld + head * D;
-    va[i] = from_f32<T>(x1 * c2 - x2 * s2);
-    va[i + half] = from_f32<T>(x2 * c2 + x1 * s2);
+// thread per (row, head, 8 consecutive pairs i..i+7): (x_i, x_{i+D/2}) ->
+// (x_i c - x_{i+D/2} s, x_{i+D/2} c + x_i s), 16- or 32-byte accesses (D/2 a multiple of 8)
+template <typename T> struct Vec8;
+template <> struct Vec8<bf16_t> {
+  __device__ static void load(const bf16_t* p, float* x) {
+    const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      x[2 * q] = bf2f((bf16_t)(v[q] & 0xffffu));
+      x[2 * q + 1] = bf2f((bf16_t)(v[q] >> 16));
+    }
   }
-  v[i] = from_f32<T>(x1 * c - x2 * s);
-  v[i + half] = from_f32<T>(x2 * c + x1 * s);
+  __device__ static void store(bf16_t* p, const float* x) {
+    u32x4 v;
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = pack_bf16x2(x[2 * q], x[2 * q + 1]);
+    *reinterpret_cast<u32x4*>(p) = v;
+  }
+};
+template <> struct Vec8<float> {
+  __device__ static void load(const float* p, float* x) {
+    const f32x4 a = *reinterpret_cast<const f32x4*>(p), b = *reinterpret_cast<const f32x4*>(p + 4);
+#pragma unroll
+    for (int q = 0; q < 4; q++) { x[q] = a[q]; x[4 + q] = b[q]; }
+  }
+  __device__ static void store(float* p, const float* x) {
+    *reinterpret_cast<f32x4*>(p) = f32x4{x[0], x[1], x[2], x[3]};
+    *reinterpret_cast<f32x4*>(p + 4) = f32x4{x[4], x[5], x[6], x[7]};
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void rope_kernel(T* __restrict__ qkv, int64_t ld, int n_rows, int n_heads, int H,
+                                                   int D, const int32_t* __restrict__ pos,
+                                                   const float* __restrict__ cos_t, const float* __restrict__ sin_t,
+                                                   T* __restrict__ q_alt, const int32_t* __restrict__ shift) {
+  const int half = D / 2, groups = half / 8;
+  const int per_row = n_heads * groups;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= per_row * n_rows) return;
+  const int row = gid / per_row, rem = gid - row * per_row;
+  const int head = rem / groups, i = (rem - head * groups) * 8;
+  T* v = qkv + (int64_t)row * ld + head * D;
+  float x1[8], x2[8], c[8], s[8], y1[8], y2[8];
+  Vec8<T>::load(v + i, x1);
+  Vec8<T>::load(v + i + half, x2);
+  const int p = pos[row];
+  Vec8<float>::load(cos_t + (int64_t)p * half + i, c);
+  Vec8<float>::load(sin_t + (int64_t)p * half + i, s);
+  if (q_alt && head < H && shift[row] >= 0) {
+    const int p2 = p - shift[row];
+    float c2[8], s2[8];
+    Vec8<float>::load(cos_t + (int64_t)p2 * half + i, c2);
+    Vec8<float>::load(sin_t + (int64_t)p2 * half + i, s2);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      y1[e] = x1[e] * c2[e] - x2[e] * s2[e];
+      y2[e] = x2[e] * c2[e] + x1[e] * s2[e];
+    }
+    T* va = q_alt + (int64_t)row * ld + head * D;
+    Vec8<T>::store(va + i, y1);
+    Vec8<T>::store(va + i + half, y2);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    y1[e] = x1[e] * c[e] - x2[e] * s[e];
+    y2[e] = x2[e] * c[e] + x1[e] * s[e];
+  }
+  Vec8<T>::store(v + i, y1);
+  Vec8<T>::store(v + i + half, y2);
 }
 
 hipError_t rope_qk(int dt, void* qkv, int64_t ld, int n_rows, int H, int Hkv, int D, const int32_t* pos,
                    const float* cos_tab, const float* sin_tab, void* q_alt, const int32_t* alt_shift,
                    hipStream_t st) {
   if (n_rows <= 0) return hipSuccess;
-  int64_t total = (int64_t)n_rows * (H + Hkv) * (D / 2);
+  if ((D / 2) % 8 || ld % 8) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)n_rows * (H + Hkv) * (D / 16);
+  if (total > 0x7fffffff) return hipErrorInvalidValue;
   dim3 grid((unsigned)((total + 255) / 256));
   if (dt == DT_F32)
     hipLaunchKernelGGL(rope_kernel<float>, grid, dim3(256), 0, st, (float*)qkv, ld, n_rows, H + Hkv, H, D, pos, cos_tab,

@@ -28,7 +28,16 @@ namespace kvop {
 // NS = 0: slabs staged through registers (two LDS buffers); NS >= 2: slabs fetched by
 // direct global -> LDS loads into NS buffers, completion tracked with explicit vmcnt waits
 // (every thread issues the same number of loads per slab), K a multiple of BK.
-template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW, int NS>
+//
+// PP != 0 (direct loads, two buffers, eight wavefronts): ping-pong schedule.  The
+// wavefronts form two groups of four with one wavefront of each group on every SIMD
+// (PP = 1: group = wave / 4, PP = 2: group = wave % 2).  Each K half-slab (KSUB) is a
+// read phase (this wavefront's A and B fragments from LDS) and an MFMA phase; group 1
+// runs one phase behind group 0, with a workgroup barrier between phases, so on every
+// SIMD one wavefront issues MFMAs while the other reads LDS.  Group 0 fetches the A part
+// of each slab, group 1 the B part, both into the buffer freed one slab earlier.
+template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW, int NS,
+          int PP = 0>
 __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
                                                       int64_t ldb, int64_t ldc, int tiles_m) {
@@ -103,11 +112,28 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
     }
   };
 
+  // Accumulators start at zero, or for the residual add at the residual itself: its reads
+  // (in the accumulator layout, lane -> C[.. + 4*(lane/16) + r][.. + lane%16]) then overlap
+  // the first slabs instead of a read-modify-write pass after the last one.
   f32x4 acc[MI][NI];
+  if constexpr (EPI == EPI_ADD) {
+    const float* Cf = reinterpret_cast<const float*>(Cv);
+    const int rb0 = m0 + wm * WM + 4 * (tid >> 4 & 3), cb0 = n0 + wn * WN + (tid & 15);
 #pragma unroll
-  for (int i = 0; i < MI; i++)
+    for (int i = 0; i < MI; i++)
 #pragma unroll
-    for (int j = 0; j < NI; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < NI; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          const int row = rb0 + 16 * i + r, col = cb0 + 16 * j;
+          acc[i][j][r] = (row < M && col < N) ? Cf[(int64_t)row * ldc + col] : 0.f;
+        }
+  } else {
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+      for (int j = 0; j < NI; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
 
   const int nk = (K + BK - 1) / BK;
   const int lrow = lane & 15, lg = lane >> 4;
@@ -134,6 +160,81 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
       __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
     }
   };
+  if constexpr (PP != 0) {
+    static_assert(NW == 8 && NS == 2 && BK % KSUB == 0 && sizeof(T) == 2, "ping-pong: 8 waves, 2 buffers, BF16");
+    constexpr int HS = BK / KSUB;                   // read/MFMA phase pairs per slab
+    constexpr int ACG = BM * CPR / 256;
+    static_assert(ACG * 256 == BM * CPR, "group split");
+    // wave-uniform by construction (scalar registers): the group branches below hold
+    // barriers and must be taken or skipped by whole wavefronts
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int grp = PP == 1 ? wv >> 2 : wv & 1;
+    const int gw = PP == 1 ? wv & 3 : wv >> 1;      // wavefront index inside the group
+    const int gt = 64 * gw + lane;
+    // this group's part of slab k0 into buffer bf (A for group 0, B for group 1)
+    static_assert(BM == BN, "both groups fetch equal parts");
+    const T* src = grp == 0 ? A : B;
+    const int64_t lds_ = grp == 0 ? lda : ldb;
+    const int row0 = grp == 0 ? m0 : n0, row_last = (grp == 0 ? M : N) - 1;
+    const int part = grp == 0 ? 0 : BM * LDK;
+    auto dma_part = [&](int k0, int bf) __attribute__((always_inline)) {
+      T* P = smem + bf * STAGE + part;
+#pragma unroll
+      for (int i = 0; i < ACG; i++) {
+        const int f = gt + 256 * i, r = f / CPR, c = slot(r, f % CPR);
+        const uint8_t* g = reinterpret_cast<const uint8_t*>(src + (int64_t)min(row0 + r, row_last) * lds_ + k0 + c * VEC);
+        uint8_t* l = reinterpret_cast<uint8_t*>(P + (256 * i + 64 * gw) * VEC);
+        __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
+      }
+    };
+    auto phase_end = [] {
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    constexpr int VM0 = (7 << 4) | (15 << 8);       // s_waitcnt vmcnt(0)
+    constexpr int LGKM0 = 0xC07F;                   // s_waitcnt lgkmcnt(0)
+    // slab 0 resident; slab 1 in flight (group 1 issues its part in its offset phase)
+    dma_part(0, 0);
+    __builtin_amdgcn_s_waitcnt(VM0);
+    phase_end();
+    if (grp == 1) {
+      if (nk > 1) dma_part(BK, 1);
+      phase_end();
+    }
+    const int H = nk * HS;
+    for (int h = 0; h < H; h++) {
+      const int kt = h / HS, hs = h % HS, bf = kt & 1;
+      // read phase.  A buffer is refilled only after a barrier that follows the last
+      // phase reading it: slab kt + 1 goes to the buffer slab kt - 1 occupied.
+      if (grp == 0 && hs == 0 && kt + 1 < nk) dma_part((kt + 1) * BK, bf ^ 1);
+      const T* As = smem + bf * STAGE + (wm * WM) * LDK;
+      const T* Bs = smem + bf * STAGE + BM * LDK + (wn * WN) * LDK;
+      u32x4 af[MI], bfr[NI];
+#pragma unroll
+      for (int i = 0; i < MI; i++)
+        af[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
+#pragma unroll
+      for (int j = 0; j < NI; j++)
+        bfr[j] = *reinterpret_cast<const u32x4*>(Bs + (j * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
+      __builtin_amdgcn_s_waitcnt(LGKM0);
+      // the next slab's part of group 1 has landed before the barrier that opens its reads
+      if (grp == 1 && hs == HS - 1 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(VM0);
+      phase_end();
+      // MFMA phase
+      if (grp == 1 && hs == HS - 1 && kt + 2 < nk) dma_part((kt + 2) * BK, bf);
+      __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+      for (int i = 0; i < MI; i++)
+#pragma unroll
+        for (int j = 0; j < NI; j++)
+          acc[i][j] = mfma_bf16(__builtin_bit_cast(u16x8, af[i]), __builtin_bit_cast(u16x8, bfr[j]), acc[i][j]);
+      __builtin_amdgcn_s_setprio(0);
+      if (grp == 0 && hs == HS - 1 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(VM0);
+      phase_end();
+    }
+    if (grp == 0) phase_end();   // group 1's last MFMA phase
+  } else {
   int buf = 0;
   if constexpr (NS == 0) {
     gload(0);
@@ -191,13 +292,15 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
       buf ^= 1;
     }
   }
+  }
   if constexpr (NS != 0) __syncthreads();  // every wavefront is done with the slabs (LDS reused below)
 
   // ---- epilogue.  Lane holds C[row0 + 4*(lane/16) + r][col0 + 16*j + lane%16].  Output
   // columns of one 16-row slab are first formed in registers (SwiGLU pairs gate block j with
   // up block j+1), staged row-major through this wavefront's slice of LDS (free after the
-  // last barrier), then written with 16-byte row-contiguous accesses (FP32 residual add:
-  // 16-byte read-modify-write).  A ragged column edge or an unaligned C uses scalar accesses.
+  // last barrier), then written with 16-byte row-contiguous accesses (the residual add has
+  // its sum in the accumulators already).  A ragged column edge or an unaligned C uses
+  // scalar accesses.
   constexpr int OW = EPI == EPI_SWIGLU ? WN / 2 : WN;       // output columns per wavefront
   constexpr int OJ = OW / 16;                               // 16-column output blocks
   constexpr int EP = OW + 4;                                // LDS slab pitch (floats)
@@ -233,10 +336,7 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
       const float* e = E + rr * EP + cc;
       if (row < M) {
         if (vec_ok && col + VW <= n_out) {
-          if constexpr (EPI == EPI_ADD) {
-            f32x4* C = reinterpret_cast<f32x4*>(reinterpret_cast<float*>(Cv) + (int64_t)row * ldc + col);
-            *C = *C + *reinterpret_cast<const f32x4*>(e);
-          } else if constexpr (OUT_BF16) {
+          if constexpr (OUT_BF16) {
             u32x4 pk;
 #pragma unroll
             for (int q = 0; q < 4; q++) pk[q] = pack_bf16x2(e[2 * q], e[2 * q + 1]);
@@ -249,8 +349,7 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
 #pragma unroll
           for (int q = 0; q < VW; q++) {
             if (col + q >= n_out) break;
-            if constexpr (EPI == EPI_ADD) reinterpret_cast<float*>(Cv)[(int64_t)row * ldc + col + q] += e[q];
-            else reinterpret_cast<TO*>(Cv)[(int64_t)row * ldc + col + q] = from_f32<TO>(e[q]);
+            reinterpret_cast<TO*>(Cv)[(int64_t)row * ldc + col + q] = from_f32<TO>(e[q]);
           }
         }
       }
@@ -292,9 +391,12 @@ static const TileCfg kBf16Tiles[] = {
     {256, 256, 32, 64, 128, 3, 8, 3, "bf16_256x256x32_8w_w64x128_swz3_lds3"},
     {256, 256, 32, 64, 128, 3, 8, 4, "bf16_256x256x32_8w_w64x128_swz3_lds4"},
     {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pp"},
+    {256, 256, 64, 64, 128, 1, 8, 2, "bf16_256x256x64_8w_w64x128_swz1_lds2_pp"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pp2"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 20; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 23; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -309,11 +411,12 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
   return true;
 }
 
-template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0>
+template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0,
+          int PP = 0>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
   size_t lds = (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS>;
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, PP>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -355,7 +458,10 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 16: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8, 2>(A, B, C, s, st);
       case 17: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 3>(A, B, C, s, st);
       case 18: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 4>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2>(A, B, C, s, st);
+      case 19: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2>(A, B, C, s, st);
+      case 20: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st);
+      case 21: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8, 2, 1>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 2>(A, B, C, s, st);
     }
   }
 }

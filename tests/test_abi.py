@@ -72,10 +72,10 @@ def test_tuning_table_text_roundtrip():
 
 
 def test_attention_kernel_knob_is_host_state_and_checked():
-    assert K.kvop_get_attention_kernel() == 0          # default: direct loads, 64-key tiles, 2 stages
-    for v in (-1, 1, 2, 0):
+    assert K.kvop_get_attention_kernel() == 2          # default: direct loads, 32-key tiles, 3 stages
+    for v in (-1, 0, 1, 2):
         K.kvop_set_attention_kernel(v)
         assert K.kvop_get_attention_kernel() == v
     with pytest.raises(K.KvopError):
         K.kvop_set_attention_kernel(3)
-    assert K.kvop_get_attention_kernel() == 0
+    assert K.kvop_get_attention_kernel() == 2

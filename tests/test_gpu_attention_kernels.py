@@ -20,9 +20,10 @@ SHAPE64 = synth.ModelShape(n_layers=2, d_model=256, n_heads=4, n_kv_heads=2, hea
 
 @pytest.fixture
 def attention_kernel():
-    """Sets the process-wide attention kernel for one test and restores the default."""
+    """Sets the process-wide attention kernel for one test and restores the one before."""
+    before = K.kvop_get_attention_kernel()
     yield K.kvop_set_attention_kernel
-    K.kvop_set_attention_kernel(0)
+    K.kvop_set_attention_kernel(before)
 
 
 def _run_filter(shape, w, docs, suffix, kv, variant, set_kernel, rs):

@@ -27,7 +27,8 @@ def _bf16(x):
 def test_gemm_every_tile_matches_float64(device, dtype, epi):
     rng = np.random.default_rng(0)
     dt = K.KVOP_F32 if dtype == "f32" else K.KVOP_BF16
-    shapes = [(1, 128, 64), (77, 256, 192), (300, 384, 256), (1000, 128, 512)]
+    # K slabs of 64: 1, 2, 3, 4 and 8; several 256-row and 256-column tiles with ragged edges
+    shapes = [(1, 128, 64), (520, 512, 128), (77, 256, 192), (300, 384, 256), (1000, 128, 512)]
     if epi != 2:
         shapes.append((37, 198, 96))       # ragged column edge, rows not 16-byte aligned
     for M, N, Kd in shapes:
