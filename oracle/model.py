@@ -69,10 +69,13 @@ def silu(x: np.ndarray) -> np.ndarray:
     return x / (1.0 + np.exp(-x))
 
 
-def attention(q: np.ndarray, K: np.ndarray, V: np.ndarray, visible: np.ndarray) -> np.ndarray:
+def attention(q: np.ndarray, K: np.ndarray, V: np.ndarray, visible: np.ndarray, pround=None) -> np.ndarray:
     """Grouped-query attention.  q [H, n, D]; K, V [Hkv, m, D]; visible [n, m] bool.
 
-    Query head h uses key/value head floor(h * Hkv / H)."""
+    Query head h uses key/value head floor(h * Hkv / H).  pround, when given, is a number
+    format applied to the unnormalised probabilities exp(s - max) before they multiply V
+    (the normaliser keeps the exact ones); it serves the emulation of a reduced-precision
+    form and is off in the plain oracle."""
     H, n, D = q.shape
     Hkv = K.shape[0]
     out = np.empty_like(q)
@@ -80,7 +83,11 @@ def attention(q: np.ndarray, K: np.ndarray, V: np.ndarray, visible: np.ndarray) 
         kh = (h * Hkv) // H
         s = (q[h] @ K[kh].T) / np.sqrt(D)
         s = np.where(visible, s, -np.inf)
-        out[h] = softmax(s, axis=-1) @ V[kh]
+        if pround is None:
+            out[h] = softmax(s, axis=-1) @ V[kh]
+        else:
+            e = np.exp(s - np.max(s, axis=-1, keepdims=True))
+            out[h] = (pround(e) @ V[kh]) / np.sum(e, axis=-1, keepdims=True)
     return out
 
 
@@ -107,10 +114,15 @@ class Model:
     'L{i}.w_up' [F, d], 'L{i}.w_down' [d, F], 'final_norm', 'embed' [V, d],
     'head' [V, d].  Linear maps apply as x @ W.T."""
 
-    def __init__(self, shape, weights: Dict[str, np.ndarray]):
+    def __init__(self, shape, weights: Dict[str, np.ndarray], act=None):
+        """act (optional): a number format (array -> array of the same shape) applied where
+        a reduced-precision implementation rounds the activations: every projection's input
+        and output, the rotated queries, the unnormalised attention probabilities and the
+        attention output.  None (the oracle proper) keeps float64 throughout."""
         self.s = Shape(shape.n_layers, shape.d_model, shape.n_heads, shape.n_kv_heads,
                        shape.head_dim, shape.d_ffn, shape.vocab, shape.rms_eps, shape.rope_theta)
         self.w = {k: np.asarray(v, np.float64) for k, v in weights.items()}
+        self.act = act
 
     def L(self, i: int, name: str) -> np.ndarray:
         return self.w[f"L{i}.{name}"]
@@ -122,20 +134,21 @@ class Model:
     def layer(self, i, x, pos, ctxK, ctxV, visible, store=None):
         s = self.s
         n = x.shape[0]
-        h = rmsnorm(x, self.L(i, "attn_norm"), s.rms_eps)
-        q = (h @ self.L(i, "wq").T).reshape(n, s.n_heads, s.head_dim).transpose(1, 0, 2)
-        k = (h @ self.L(i, "wk").T).reshape(n, s.n_kv_heads, s.head_dim).transpose(1, 0, 2)
-        v = (h @ self.L(i, "wv").T).reshape(n, s.n_kv_heads, s.head_dim).transpose(1, 0, 2)
-        q = rope(q, pos, s.rope_theta)
+        r = self.act if self.act is not None else (lambda t: t)
+        h = r(rmsnorm(x, self.L(i, "attn_norm"), s.rms_eps))
+        q = r(h @ self.L(i, "wq").T).reshape(n, s.n_heads, s.head_dim).transpose(1, 0, 2)
+        k = r(h @ self.L(i, "wk").T).reshape(n, s.n_kv_heads, s.head_dim).transpose(1, 0, 2)
+        v = r(h @ self.L(i, "wv").T).reshape(n, s.n_kv_heads, s.head_dim).transpose(1, 0, 2)
+        q = r(rope(q, pos, s.rope_theta))
         k = rope(k, pos, s.rope_theta)
         if store is not None:
             k, v = store(k), store(v)
         K = np.concatenate([ctxK, k], axis=1)
         V = np.concatenate([ctxV, v], axis=1)
-        a = attention(q, K, V, visible)
+        a = r(attention(q, K, V, visible, self.act))
         x = x + a.transpose(1, 0, 2).reshape(n, s.n_heads * s.head_dim) @ self.L(i, "wo").T
-        h2 = rmsnorm(x, self.L(i, "ffn_norm"), s.rms_eps)
-        f = silu(h2 @ self.L(i, "w_gate").T) * (h2 @ self.L(i, "w_up").T)
+        h2 = r(rmsnorm(x, self.L(i, "ffn_norm"), s.rms_eps))
+        f = r(silu(h2 @ self.L(i, "w_gate").T) * (h2 @ self.L(i, "w_up").T))
         x = x + f @ self.L(i, "w_down").T
         return x, k, v
 

@@ -15,6 +15,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -29,16 +30,17 @@ namespace kvop {
 // direct global -> LDS loads into NS buffers, completion tracked with explicit vmcnt waits
 // (every thread issues the same number of loads per slab), K a multiple of BK.
 //
-// PP != 0 (direct loads, two buffers, eight wavefronts): ping-pong schedule.  The
-// wavefronts form two groups of four with one wavefront of each group on every SIMD
-// (PP = 1: group = wave / 4, PP = 2: group = wave % 2).  Each K half-slab (KSUB) is a
-// read phase (this wavefront's A and B fragments from LDS) and an MFMA phase; group 1
-// runs one phase behind group 0, with a workgroup barrier between phases, so on every
-// SIMD one wavefront issues MFMAs while the other reads LDS.  Group 0 fetches the A part
-// of each slab, group 1 the B part, both into the buffer freed one slab earlier.
+// SCH = 1 (direct loads): software-pipelined K loop.  The A/B fragments of the next MFMA
+// step are read from LDS into a second register set while the current step's MFMAs run,
+// and each slab's direct loads are issued between MFMAs; one workgroup barrier per slab,
+// placed where the last fragments of a slab are already in registers.
 template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW, int NS,
-          int PP = 0>
-__global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
+          int SCH = 0>
+__global__ __launch_bounds__(64 * NW)
+// pipelined 4-wavefront tiles with up to 128x64 per wavefront: registers for two resident
+// workgroups, whose barriers and epilogues then overlap each other's MFMAs
+__attribute__((amdgpu_waves_per_eu(SCH == 1 && NW == 4 && WM * WN <= 128 * 64 ? 2 : 1)))
+void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
                                                       int64_t ldb, int64_t ldc, int tiles_m) {
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
@@ -160,80 +162,93 @@ __global__ __launch_bounds__(64 * NW) void gemm_nt_kernel(const T* __restrict__ 
       __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
     }
   };
-  if constexpr (PP != 0) {
-    static_assert(NW == 8 && NS == 2 && BK % KSUB == 0 && sizeof(T) == 2, "ping-pong: 8 waves, 2 buffers, BF16");
-    constexpr int HS = BK / KSUB;                   // read/MFMA phase pairs per slab
-    constexpr int ACG = BM * CPR / 256;
-    static_assert(ACG * 256 == BM * CPR, "group split");
-    // wave-uniform by construction (scalar registers): the group branches below hold
-    // barriers and must be taken or skipped by whole wavefronts
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int grp = PP == 1 ? wv >> 2 : wv & 1;
-    const int gw = PP == 1 ? wv & 3 : wv >> 1;      // wavefront index inside the group
-    const int gt = 64 * gw + lane;
-    // this group's part of slab k0 into buffer bf (A for group 0, B for group 1)
-    static_assert(BM == BN, "both groups fetch equal parts");
-    const T* src = grp == 0 ? A : B;
-    const int64_t lds_ = grp == 0 ? lda : ldb;
-    const int row0 = grp == 0 ? m0 : n0, row_last = (grp == 0 ? M : N) - 1;
-    const int part = grp == 0 ? 0 : BM * LDK;
-    auto dma_part = [&](int k0, int bf) __attribute__((always_inline)) {
-      T* P = smem + bf * STAGE + part;
-#pragma unroll
-      for (int i = 0; i < ACG; i++) {
-        const int f = gt + 256 * i, r = f / CPR, c = slot(r, f % CPR);
-        const uint8_t* g = reinterpret_cast<const uint8_t*>(src + (int64_t)min(row0 + r, row_last) * lds_ + k0 + c * VEC);
-        uint8_t* l = reinterpret_cast<uint8_t*>(P + (256 * i + 64 * gw) * VEC);
-        __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
-      }
-    };
-    auto phase_end = [] {
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_barrier();
-      __builtin_amdgcn_sched_barrier(0);
-    };
-    constexpr int VM0 = (7 << 4) | (15 << 8);       // s_waitcnt vmcnt(0)
-    constexpr int LGKM0 = 0xC07F;                   // s_waitcnt lgkmcnt(0)
-    // slab 0 resident; slab 1 in flight (group 1 issues its part in its offset phase)
-    dma_part(0, 0);
-    __builtin_amdgcn_s_waitcnt(VM0);
-    phase_end();
-    if (grp == 1) {
-      if (nk > 1) dma_part(BK, 1);
-      phase_end();
-    }
-    const int H = nk * HS;
-    for (int h = 0; h < H; h++) {
-      const int kt = h / HS, hs = h % HS, bf = kt & 1;
-      // read phase.  A buffer is refilled only after a barrier that follows the last
-      // phase reading it: slab kt + 1 goes to the buffer slab kt - 1 occupied.
-      if (grp == 0 && hs == 0 && kt + 1 < nk) dma_part((kt + 1) * BK, bf ^ 1);
+  if constexpr (SCH == 1) {
+    static_assert(NS >= 2 && sizeof(T) == 2 && (BK == KSUB || BK == 2 * KSUB),
+                  "pipelined: direct loads, BF16, one or two MFMA steps per slab");
+    constexpr int HS = BK / KSUB;                     // MFMA steps per slab
+    constexpr int OPS = ACH + BCH;                    // direct loads per thread per slab
+    constexpr int VMW = (NS - 2) * OPS, VMP = (NS - 1) * OPS;
+    static_assert(VMP <= 63, "vmcnt range");
+    constexpr int VM_STEADY = (VMW & 15) | ((VMW >> 4) << 14) | (7 << 4) | (15 << 8);
+    constexpr int VM_FIRST = (VMP & 15) | ((VMP >> 4) << 14) | (7 << 4) | (15 << 8);
+    constexpr int LGKM0 = 0xC07F;
+    // fragments of step hs of the slab in buffer bf
+    auto rd = [&](int bf, int hs, u32x4* a_, u32x4* b_) __attribute__((always_inline)) {
       const T* As = smem + bf * STAGE + (wm * WM) * LDK;
       const T* Bs = smem + bf * STAGE + BM * LDK + (wn * WN) * LDK;
-      u32x4 af[MI], bfr[NI];
 #pragma unroll
       for (int i = 0; i < MI; i++)
-        af[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
+        a_[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
 #pragma unroll
       for (int j = 0; j < NI; j++)
-        bfr[j] = *reinterpret_cast<const u32x4*>(Bs + (j * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
-      __builtin_amdgcn_s_waitcnt(LGKM0);
-      // the next slab's part of group 1 has landed before the barrier that opens its reads
-      if (grp == 1 && hs == HS - 1 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(VM0);
-      phase_end();
-      // MFMA phase
-      if (grp == 1 && hs == HS - 1 && kt + 2 < nk) dma_part((kt + 2) * BK, bf);
-      __builtin_amdgcn_s_setprio(1);
+        b_[j] = *reinterpret_cast<const u32x4*>(Bs + (j * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
+    };
+    // Every slab boundary issues exactly one slab of direct loads (past the last slab they
+    // re-read slab nk - 1 into the buffer just freed, which is never read again), so the
+    // number of loads in flight behind any slab is fixed and a step has no branches: one
+    // basic block per step, free for the scheduler to interleave.
+#pragma unroll
+    for (int q = 0; q < NS; q++) dma(min(q, nk - 1) * BK, q);
+    __builtin_amdgcn_s_waitcnt(VM_FIRST);             // slab 0 landed (this thread's part)
+    __builtin_amdgcn_s_barrier();                     // ... and every thread's
+    __builtin_amdgcn_sched_barrier(0);
+    // one MFMA step: fragments c* (read during the previous step) feed the MFMAs while the
+    // next step's fragments are read into n*; a step that ends a slab (HSV == HS - 1) first
+    // waits for the next slab, passes the barrier and refills the buffer just consumed
+    auto step = [&](int kt, auto hs_c, u32x4* ca, u32x4* cb, u32x4* na, u32x4* nb) __attribute__((always_inline)) {
+      constexpr int HSV = decltype(hs_c)::value;
+      int nbf = kt % NS, nhs = HSV + 1;
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (HSV == HS - 1) {
+        // slab kt + 1 visible, slab kt's buffer free (all its fragments are in registers)
+        __builtin_amdgcn_s_waitcnt(VM_STEADY);
+        __builtin_amdgcn_s_waitcnt(LGKM0);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        dma(min(kt + NS, nk - 1) * BK, kt % NS);
+        nbf = min(kt + 1, nk - 1) % NS;
+        nhs = 0;
+      }
+      rd(nbf, nhs, na, nb);
 #pragma unroll
       for (int i = 0; i < MI; i++)
 #pragma unroll
         for (int j = 0; j < NI; j++)
-          acc[i][j] = mfma_bf16(__builtin_bit_cast(u16x8, af[i]), __builtin_bit_cast(u16x8, bfr[j]), acc[i][j]);
-      __builtin_amdgcn_s_setprio(0);
-      if (grp == 0 && hs == HS - 1 && kt + 1 < nk) __builtin_amdgcn_s_waitcnt(VM0);
-      phase_end();
+          acc[i][j] = mfma_bf16(__builtin_bit_cast(u16x8, ca[i]), __builtin_bit_cast(u16x8, cb[j]), acc[i][j]);
+      // issue order: an MFMA first (its fragments are the previous step's reads), then the
+      // slab's direct loads and the next step's LDS reads, one per MFMA, so that their
+      // latency hides behind this step's remaining MFMAs
+      if constexpr (HSV == HS - 1) {
+#pragma unroll
+        for (int q = 0; q < OPS; q++) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+          __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // VMEM read
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < MI + NI; q++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);     // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);     // DS read
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, MI * NI, 0);  // the remaining MFMAs
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    u32x4 fa0[MI], fb0[NI], fa1[MI], fb1[NI];
+    rd(0, 0, fa0, fb0);
+    if constexpr (HS == 2) {
+      for (int kt = 0; kt < nk; kt++) {
+        step(kt, I0{}, fa0, fb0, fa1, fb1);
+        step(kt, I1{}, fa1, fb1, fa0, fb0);
+      }
+    } else {
+      for (int kt = 0; kt < nk; kt += 2) {
+        step(kt, I0{}, fa0, fb0, fa1, fb1);
+        if (kt + 1 < nk) step(kt + 1, I0{}, fa1, fb1, fa0, fb0);
+      }
     }
-    if (grp == 0) phase_end();   // group 1's last MFMA phase
   } else {
   int buf = 0;
   if constexpr (NS == 0) {
@@ -391,12 +406,13 @@ static const TileCfg kBf16Tiles[] = {
     {256, 256, 32, 64, 128, 3, 8, 3, "bf16_256x256x32_8w_w64x128_swz3_lds3"},
     {256, 256, 32, 64, 128, 3, 8, 4, "bf16_256x256x32_8w_w64x128_swz3_lds4"},
     {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2"},
-    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pp"},
-    {256, 256, 64, 64, 128, 1, 8, 2, "bf16_256x256x64_8w_w64x128_swz1_lds2_pp"},
-    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pp2"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pipe"},
+    {256, 128, 32, 128, 64, 3, 4, 3, "bf16_256x128x32_w128x64_swz3_lds3_pipe"},
+    {128, 256, 32, 64, 128, 3, 4, 3, "bf16_128x256x32_w64x128_swz3_lds3_pipe"},
+    {256, 128, 32, 128, 64, 3, 4, 2, "bf16_256x128x32_w128x64_swz3_lds2_pipe"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 23; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 24; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -412,11 +428,11 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
 }
 
 template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0,
-          int PP = 0>
+          int SCH = 0>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
   size_t lds = (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, PP>;
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, SCH>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -460,8 +476,9 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 18: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 4>(A, B, C, s, st);
       case 19: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2>(A, B, C, s, st);
       case 20: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st);
-      case 21: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8, 2, 1>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 2>(A, B, C, s, st);
+      case 21: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 3, 1>(A, B, C, s, st);
+      case 22: return launch_t<T, TO, EPI, 128, 256, 32, 64, 128, 3, 4, 3, 1>(A, B, C, s, st);
+      default: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st);
     }
   }
 }
@@ -521,7 +538,7 @@ int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
   if (s.M <= 128) return 3;        // 64x128
   if (s.M < 8192) return 7;        // 128x128, 4 wavefronts
-  if (gemm_tile_ok(dt, 19, s, epi)) return 19;  // 256x256, 8 wavefronts of 128x64, direct loads
+  if (gemm_tile_ok(dt, 20, s, epi)) return 20;  // 256x256, 8 wavefronts of 128x64, direct loads, pipelined
   return 11;                       // 256x256, 8 wavefronts of 64x128
 }
 

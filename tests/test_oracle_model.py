@@ -382,3 +382,36 @@ def test_fp8_format_cache_stays_close_and_is_what_later_layers_see():
     np.testing.assert_array_equal(q.V[0], codecs.fp8_cache_roundtrip(plain.V[0]))
     assert not np.array_equal(q.K[1], codecs.fp8_cache_roundtrip(plain.K[1]))
     assert rel_err(q.K, plain.K) < 0.1
+
+
+def test_reduced_precision_form_hooks():
+    """The activation-format hook of the oracle (used to emulate the BF16 form): an identity
+    format reproduces the plain oracle up to FP64 reordering; the format is applied at the
+    documented points, 8 per layer plus the probabilities of every query head; and the
+    layer-0 keys of a BF16 emulation are exactly the BF16 rounding of the rotated BF16-rounded
+    projection (RNE at every point, as the kernels round)."""
+    from oracle import codecs
+    m = micro_model(seed=6)
+    doc = _doc(m, 30, 15)
+    plain = om.kv_build(m, doc)
+    ident = om.kv_build(om.Model(MICRO, m.w, act=lambda t: t), doc)
+    np.testing.assert_allclose(ident.K, plain.K, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(ident.pooled, plain.pooled, rtol=0, atol=1e-12)
+    calls = []
+
+    def spy(t):
+        calls.append(t.shape)
+        return t
+
+    ms = om.Model(MICRO, m.w, act=spy)
+    x = m.w["embed"][np.asarray(doc)]
+    pos = np.arange(len(doc), dtype=np.float64)
+    causal = np.tril(np.ones((len(doc), len(doc)), bool))
+    ms.layer(0, x, pos, ms.empty_ctx(), ms.empty_ctx(), causal)
+    assert len(calls) == 8 + MICRO.n_heads
+    mb = om.Model(MICRO, m.w, act=codecs.bf16_round)
+    cb = om.kv_build(mb, doc, store=codecs.bf16_round)
+    h = codecs.bf16_round(om.rmsnorm(x, m.L(0, "attn_norm"), MICRO.rms_eps))
+    k = codecs.bf16_round(h @ m.L(0, "wk").T).reshape(len(doc), MICRO.n_kv_heads, MICRO.head_dim).transpose(1, 0, 2)
+    np.testing.assert_array_equal(cb.K[0], codecs.bf16_round(om.rope(k, pos, MICRO.rope_theta)))
+    assert not np.array_equal(cb.K[1], plain.K[1])
