@@ -119,6 +119,46 @@ kvop_status kvop_pool_stats(const kvop_pool* pool, uint64_t* used_bytes, uint64_
 kvop_status kvop_kv_build(kvop_pool* pool, const int32_t* tokens_dev, const int64_t* offsets_host,
                           int32_t n_docs, void* stream, kvop_handle* handles_out, float* pooled_dev);
 
+/* Offline cache creation with query-agnostic compression scores (Section 2.3 and Section 5,
+ * "Offline": the compressed profiles keep the rows chosen by the Expected Attention method
+ * the paper cites).  Builds the caches exactly as kvop_kv_build (same handles, same cache
+ * contents) and also writes, per document row, its expected-attention score:
+ *   n_future   : the future queries sit at positions L .. L+n_future-1 (1..4096; e.g. the
+ *                operators' suffix length); L + n_future must not exceed 65536
+ *   scores_dev : FP32 [offsets[n_docs] - offsets[0]] (device), indexed like tokens_dev
+ *                from offsets[0]; row score = sum over layers and kv heads of the row's
+ *                share of that (layer, kv head)'s expected attention contribution: the
+ *                document's pre-rotation queries of each layer and query head taken as a
+ *                Gaussian (mean, population covariance), mapped through the rotation
+ *                averaged over the future positions; a rotated key k's expected weight is
+ *                exp(mean.k/sqrt(D) + k^T cov k/(2D)) normalised over the document's keys,
+ *                times |v|, averaged over the query heads of the kv head, and each (layer,
+ *                kv head) totals 1 (so a document's scores total n_layers * n_kv_heads).
+ * Errors as kvop_kv_build, plus EINVAL (null scores_dev, n_future out of range, L + n_future
+ * too long) and ENOMEM (workspace).  Asynchronous on stream like kvop_kv_build. */
+kvop_status kvop_kv_build_scored(kvop_pool* pool, const int32_t* tokens_dev, const int64_t* offsets_host,
+                                 int32_t n_docs, int32_t n_future, void* stream, kvop_handle* handles_out,
+                                 float* pooled_dev, float* scores_dev);
+
+/* Rows kept at retention r of a document of length L (the profile's compression ratio is
+ * 1 - r): k = clamp(floor((round(1000 r) * L + 500) / 1000), min(4, L), L).  -1 if L < 1 or
+ * r outside [0, 1]. */
+int32_t kvop_retained_count(float r, int64_t L);
+
+/* Retained-row lists of a compressed profile from expected-attention scores: per document
+ * the kvop_retained_count(r, L) rows of highest score (equal scores: lower row first),
+ * ascending, in the list format kvop_op_eval takes.
+ *   scores_dev      : FP32 scores as written by kvop_kv_build_scored (device), indexed from
+ *                     offsets_host[0]
+ *   offsets_host    : int64[n_docs+1] document row offsets (as for kvop_kv_build)
+ *   idx_dev         : int32 output (device), room for the sum of the counts
+ *   idx_offsets_out : int64[n_docs+1] host output: document i's list is
+ *                     idx[idx_offsets[i] : idx_offsets[i+1]] (document-relative rows)
+ * Uses the pool's model for metadata staging.  Errors: EINVAL (null pointers, r outside
+ * [0, 1], a document length outside [1, 65535]).  Asynchronous on stream. */
+kvop_status kvop_ea_select(kvop_pool* pool, const float* scores_dev, const int64_t* offsets_host, int32_t n_docs,
+                           float r, void* stream, int32_t* idx_dev, int64_t* idx_offsets_out);
+
 /* Release documents' caches; their handles become invalid.  EBADHANDLE if any
  * handle is not live in this pool (then nothing is released). */
 kvop_status kvop_kv_release(kvop_pool* pool, const kvop_handle* handles, int32_t n);

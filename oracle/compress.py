@@ -93,9 +93,10 @@ def ea_scores(m: om.Model, tokens, n_future: int) -> np.ndarray:
     pos = np.arange(L, dtype=np.float64)
     causal = np.tril(np.ones((L, L), dtype=bool))
     score = np.zeros(L)
+    r = m.act if m.act is not None else (lambda t: t)   # the model's activation format, as in its layers
     for i in range(s.n_layers):
-        h = om.rmsnorm(x, m.L(i, "attn_norm"), s.rms_eps)
-        qt = (h @ m.L(i, "wq").T).reshape(L, s.n_heads, s.head_dim).transpose(1, 0, 2)
+        h = r(om.rmsnorm(x, m.L(i, "attn_norm"), s.rms_eps))
+        qt = r(h @ m.L(i, "wq").T).reshape(L, s.n_heads, s.head_dim).transpose(1, 0, 2)
         x, k, v = m.layer(i, x, pos, m.empty_ctx(), m.empty_ctx(), causal)
         score += layer_contributions(qt, k, v, L, n_future, s.rope_theta).sum(axis=0)
     return score

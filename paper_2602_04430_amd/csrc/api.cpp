@@ -28,10 +28,10 @@ int64_t g_wave_rows = 131072;  // suffix rows per op_eval / mixed wave
 // ---- optional per-kernel-class timing: HIP events recorded on the caller's stream around
 // each launch while profiling is on; read back (synchronising) by kvop_profile_stop.
 enum ProfClass { PC_GEMM_QKV, PC_GEMM_O, PC_GEMM_GATEUP, PC_GEMM_DOWN, PC_ATTENTION, PC_ROPE_KV, PC_RMSNORM,
-                 PC_EMBED, PC_HEAD, PC_DECODE, PC_OTHER, PC_COUNT };
+                 PC_EMBED, PC_HEAD, PC_DECODE, PC_EA, PC_OTHER, PC_COUNT };
 // map_decode: one whole greedy decode step (all layers) of a map operator
 const char* kProfNames[PC_COUNT] = {"gemm_qkv", "gemm_o", "gemm_gate_up", "gemm_down", "attention", "rope_kv",
-                                    "rmsnorm", "embed", "head", "map_decode", "other"};
+                                    "rmsnorm", "embed", "head", "map_decode", "ea_scores", "other"};
 struct Prof {
   bool on = false;
   bool capturing = false;  // no event records while a graph is being captured
@@ -126,6 +126,7 @@ struct kvop_model {
   // workspaces shared by kv_build and op_eval (calls on one model are serialised)
   DevBuf ws;
   DevBuf meta;
+  DevBuf ea;  // expected-attention workspace of kvop_kv_build_scored
   HostStage stage;
   int* dflag = nullptr;   // [0]: list-validation count, [16]: persistent-attention unit counter
   int* hflag = nullptr;
@@ -253,6 +254,11 @@ struct LayerPlan {
   int own_kcol, own_vcol;
   int n_groups;                    // selection groups (all rows: one group {rows, 1, 0})
   SelGroup sel[kMaxSelGroups];
+  // expected-attention scoring during prefill (off when ea_row_off is null)
+  const int64_t* ea_row_off = nullptr;
+  int ea_nd = 0, ea_n_future = 0;
+  float* ea_e = nullptr;
+  float* ea_acc = nullptr;
   void select_all() { n_groups = 1; sel[0] = SelGroup{rows, 1, 0}; }
   void select_one(int n, int stride, int off) { n_groups = 1; sel[0] = SelGroup{n, stride, off}; }
 };
@@ -272,6 +278,11 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
     ProfScope ps(PC_GEMM_QKV, st);
     GemmShape s{rows, qc, d, d, d, qc};
     HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.qkv, s, st));
+  }
+  if (lp.ea_row_off) {  // before the rotation: the statistics are of the pre-rotation queries
+    ProfScope ps(PC_EA, st);
+    HIPTRY(ea_layer(dt, D, b.qkv, qc, H, Hkv, lp.ea_row_off, lp.ea_nd, lp.ea_n_future, m->cos_tab, m->sin_tab,
+                    lp.ea_e, lp.ea_acc, st));
   }
   if (n_kvblocks > 0) {
     ProfScope ps(PC_ROPE_KV, st);
@@ -564,8 +575,9 @@ kvop_status kvop_kv_release(kvop_pool* p, const kvop_handle* hs, int32_t n) {
 }
 
 // ------------------------------------------------------------------ kv_build
-kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* offsets, int32_t n, void* stream,
-                          kvop_handle* handles_out, float* pooled) {
+static kvop_status kv_build_impl(kvop_pool* p, const int32_t* tokens, const int64_t* offsets, int32_t n,
+                                 void* stream, kvop_handle* handles_out, float* pooled, int n_future,
+                                 float* scores) {
   if (!p || n < 0 || (n > 0 && (!tokens || !offsets || !handles_out))) return fail(KVOP_EINVAL, "bad arguments");
   if (n == 0) return KVOP_OK;
   kvop_model* m = p->m;
@@ -575,6 +587,22 @@ kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* of
     int64_t L = offsets[i + 1] - offsets[i];
     if (L < 1) return fail(KVOP_EINVAL, "document " + std::to_string(i) + " is empty or offsets decrease");
     if (L >= kRopeMaxPos) return fail(KVOP_EINVAL, "document longer than the rotary table");
+    if (scores && L + n_future > kRopeMaxPos)
+      return fail(KVOP_EINVAL, "document " + std::to_string(i) + ": L + n_future exceeds the rotary table");
+  }
+  // expected-attention workspace (model-owned, grown on demand): per chunk row, H
+  // log-weights and Hkv accumulators
+  float* ea_ws = nullptr;
+  int64_t ea_rows = 0;
+  if (scores) {
+    ea_rows = 65536;
+    for (int i = 0; i < n; i++) ea_rows = std::max<int64_t>(ea_rows, offsets[i + 1] - offsets[i]);
+    if (p->m->ea.reserve((size_t)ea_rows * (p->m->cfg.n_heads + p->m->cfg.n_kv_heads) * 4, (hipStream_t)stream) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return fail(KVOP_ENOMEM, "expected-attention workspace");
+    }
+    ea_ws = (float*)p->m->ea.p;
   }
   // allocate every region first (all or nothing)
   std::vector<uint64_t> offs(n), sizes(n);
@@ -668,6 +696,18 @@ kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* of
     lp.own_from_qkv = false;
     lp.own = nullptr;
     lp.select_all();
+    float* ea_acc = ea_ws ? ea_ws + (size_t)ea_rows * H : nullptr;
+    if (ea_ws) {
+      lp.ea_row_off = (const int64_t*)(md + o_roff);
+      lp.ea_nd = nd;
+      lp.ea_n_future = n_future;
+      lp.ea_e = ea_ws;
+      lp.ea_acc = ea_acc;
+      if (ea_zero(ea_acc, rows * Hkv, st) != hipSuccess) {
+        rollback();
+        return fail(KVOP_EDEVICE, "expected-attention launch");
+      }
+    }
     for (int l = 0; l < c.n_layers; l++) {
       bool tail = (l + 1 < c.n_layers) || pooled != nullptr;
       kvop_status s = run_layer(m, l, b, lp, p->base, p->kvdt, (const KvBlock*)(md + o_blk), (int)blocks.size(), st,
@@ -676,6 +716,10 @@ kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* of
         rollback();
         return s;
       }
+    }
+    if (ea_ws && ea_finish(ea_acc, Hkv, (int)rows, scores + (offsets[i0] - offsets[0]), st) != hipSuccess) {
+      rollback();
+      return fail(KVOP_EDEVICE, "expected-attention launch");
     }
     if (pooled) {
       if (pooled_mean(b.x, d, (const int64_t*)(md + o_roff), nd, (int)rows, m->final_norm, c.rms_eps,
@@ -704,6 +748,62 @@ kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* of
     handles_out[i] = make_handle(p, slot, s.gen);
     p->live++;
   }
+  return KVOP_OK;
+}
+
+kvop_status kvop_kv_build(kvop_pool* p, const int32_t* tokens, const int64_t* offsets, int32_t n, void* stream,
+                          kvop_handle* handles_out, float* pooled) {
+  return kv_build_impl(p, tokens, offsets, n, stream, handles_out, pooled, 0, nullptr);
+}
+
+kvop_status kvop_kv_build_scored(kvop_pool* p, const int32_t* tokens, const int64_t* offsets, int32_t n,
+                                 int32_t n_future, void* stream, kvop_handle* handles_out, float* pooled,
+                                 float* scores) {
+  if (!scores || n_future < 1 || n_future > 4096) return fail(KVOP_EINVAL, "scores output and 1 <= n_future <= 4096");
+  return kv_build_impl(p, tokens, offsets, n, stream, handles_out, pooled, n_future, scores);
+}
+
+int32_t kvop_retained_count(float r, int64_t L) {
+  if (L < 1 || !(r >= 0.f) || r > 1.f) return -1;
+  const int64_t rm = (int64_t)std::llround(1000.0 * (double)r);
+  const int64_t k = (rm * L + 500) / 1000;
+  return (int32_t)std::min<int64_t>(std::max<int64_t>(k, std::min<int64_t>(4, L)), L);
+}
+
+kvop_status kvop_ea_select(kvop_pool* p, const float* scores, const int64_t* offsets, int32_t n, float r,
+                           void* stream, int32_t* idx, int64_t* idx_offsets) {
+  if (!p || n < 0 || (n > 0 && (!scores || !offsets || !idx || !idx_offsets))) return fail(KVOP_EINVAL, "bad arguments");
+  if (!(r >= 0.f) || r > 1.f) return fail(KVOP_EINVAL, "r must lie in [0, 1]");
+  if (n == 0) return KVOP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int64_t> doc_off(n + 1), out_off(n + 1);
+  std::vector<int32_t> kc(n);
+  out_off[0] = 0;
+  for (int i = 0; i < n; i++) {
+    const int64_t L = offsets[i + 1] - offsets[i];
+    if (L < 1 || L >= kRopeMaxPos) return fail(KVOP_EINVAL, "document " + std::to_string(i) + ": bad length");
+    doc_off[i] = offsets[i] - offsets[0];
+    kc[i] = kvop_retained_count(r, L);
+    out_off[i + 1] = out_off[i] + kc[i];
+  }
+  doc_off[n] = offsets[n] - offsets[0];
+  kvop_model* m = p->m;
+  Mirror mir;
+  size_t o_doc = mir.add((n + 1) * 8), o_out = mir.add((n + 1) * 8), o_k = mir.add(n * 4);
+  if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
+    return fail(KVOP_ENOMEM, "metadata staging");
+  memcpy(m->stage.p + o_doc, doc_off.data(), (n + 1) * 8);
+  memcpy(m->stage.p + o_out, out_off.data(), (n + 1) * 8);
+  memcpy(m->stage.p + o_k, kc.data(), n * 4);
+  char* md = (char*)m->meta.p;
+  if (hipMemcpyAsync(md, m->stage.p, mir.size, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(m->stage.ev, st) != hipSuccess)
+    return fail(KVOP_EDEVICE, "metadata upload");
+  m->stage.pending = true;
+  if (ea_select(scores + offsets[0], (const int64_t*)(md + o_doc), (const int32_t*)(md + o_k),
+                (const int64_t*)(md + o_out), n, idx, st) != hipSuccess)
+    return fail(KVOP_EDEVICE, "selection launch");
+  memcpy(idx_offsets, out_off.data(), (n + 1) * 8);
   return KVOP_OK;
 }
 

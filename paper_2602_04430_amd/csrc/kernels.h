@@ -81,6 +81,22 @@ hipError_t fp8_widen(const uint8_t* codes, uint16_t* out, int n, hipStream_t st)
 void attention_set_impl(int impl);
 int attention_get_impl();
 
+// ---------------------------------------------------------------- expected-attention compression
+// One layer of a prefill chunk (rows of nd documents, chunk-relative row offsets row_off[nd+1],
+// qkv = the QKV projection before rotation, dt f32 or bf16, row stride ld): e_ws [rows][H]
+// receives every key's expected log-weight per query head, then acc [rows][Hkv] += the
+// layer's normalised contributions.  Documents need L + n_future <= the rotary table length.
+hipError_t ea_layer(int dt, int D, const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off, int nd,
+                    int n_future, const float* cos_tab, const float* sin_tab, float* e_ws, float* acc,
+                    hipStream_t st);
+hipError_t ea_zero(float* p, int64_t n, hipStream_t st);
+// out[row] = sum over kv heads of acc[row][g]
+hipError_t ea_finish(const float* acc, int Hkv, int rows, float* out, hipStream_t st);
+// per document d (scores rows doc_off[d] .. doc_off[d+1]): the kcount[d] highest scores, equal
+// scores lower row first, ascending document-relative rows written at idx + out_off[d]
+hipError_t ea_select(const float* scores, const int64_t* doc_off, const int32_t* kcount, const int64_t* out_off,
+                     int n_docs, int32_t* idx, hipStream_t st);
+
 // ---------------------------------------------------------------- elementwise / small kernels
 // x[row] = embed[tok[row]] (embed in `dt`), FP32 output; ids clamped to [0, V)
 hipError_t embed_rows(int dt, const void* embed, const int32_t* tok, int n_rows, int d, int vocab, float* x,

@@ -60,6 +60,9 @@ _SIGS = {
     "kvop_doc_bytes": (C.c_uint64, [_P, C.c_int64]),
     "kvop_pool_stats": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]),
     "kvop_kv_build": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P]),
+    "kvop_kv_build_scored": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P]),
+    "kvop_retained_count": (C.c_int32, [C.c_float, C.c_int64]),
+    "kvop_ea_select": (C.c_int, [_P, _P, _P, C.c_int32, C.c_float, _P, _P, _P]),
     "kvop_kv_release": (C.c_int, [_P, _P, C.c_int32]),
     "kvop_op_eval": (C.c_int, [_P, C.POINTER(kvop_op), C.c_float, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
     "kvop_gemm_num_tiles": (C.c_int32, [C.c_int32]),
@@ -181,6 +184,33 @@ def kvop_kv_build(pool, tokens_dev, offsets: Sequence[int], pooled_dev=None, str
     _check(lib().kvop_kv_build(pool, _dptr(tokens_dev), po, n, _stream(stream),
                                handles.ctypes.data_as(C.c_void_p), _dptr(pooled_dev)))
     return handles
+
+
+def kvop_kv_build_scored(pool, tokens_dev, offsets: Sequence[int], n_future: int, scores_dev, pooled_dev=None,
+                         stream=None) -> np.ndarray:
+    """kvop_kv_build that also writes every row's expected-attention score into scores_dev
+    (FP32, indexed like tokens_dev from offsets[0]).  Returns the handles."""
+    offs, po = _host(offsets, np.int64)
+    n = len(offs) - 1
+    handles = np.zeros(max(n, 0), np.uint64)
+    _check(lib().kvop_kv_build_scored(pool, _dptr(tokens_dev), po, n, int(n_future), _stream(stream),
+                                      handles.ctypes.data_as(C.c_void_p), _dptr(pooled_dev), _dptr(scores_dev)))
+    return handles
+
+
+def kvop_retained_count(r: float, L: int) -> int:
+    return int(lib().kvop_retained_count(float(r), int(L)))
+
+
+def kvop_ea_select(pool, scores_dev, offsets: Sequence[int], r: float, idx_dev, stream=None) -> np.ndarray:
+    """Retained lists at retention r from expected-attention scores, written into idx_dev
+    (int32, room for the total); returns the int64 list offsets (n + 1)."""
+    offs, po = _host(offsets, np.int64)
+    n = len(offs) - 1
+    out = np.zeros(max(n, 0) + 1, np.int64)
+    _check(lib().kvop_ea_select(pool, _dptr(scores_dev), po, n, float(r), _stream(stream), _dptr(idx_dev),
+                                out.ctypes.data_as(C.c_void_p)))
+    return out
 
 
 def kvop_kv_release(pool, handles) -> None:

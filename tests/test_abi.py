@@ -79,3 +79,11 @@ def test_attention_kernel_knob_is_host_state_and_checked():
     with pytest.raises(K.KvopError):
         K.kvop_set_attention_kernel(3)
     assert K.kvop_get_attention_kernel() == 2
+
+
+def test_retained_count_rule_matches_the_input_generator():
+    """The library's k(r, L) (used by kvop_ea_select) is the count rule of the seeded lists."""
+    for L in (1, 2, 3, 4, 5, 9, 10, 64, 999, 1000, 4096, 65535):
+        for r in (0.0, 0.1, 0.25, 0.3, 0.5, 0.8, 0.999, 1.0):
+            assert K.kvop_retained_count(r, L) == synth.retained_count(r, L), (r, L)
+    assert K.kvop_retained_count(0.5, 0) == -1 and K.kvop_retained_count(1.5, 10) == -1
