@@ -54,6 +54,8 @@ def main():
                     help="documents the proxy is trained on (labels from the full BF16 r=1 operator)")
     ap.add_argument("--proxy-epochs", type=int, default=20)
     ap.add_argument("--no-proxy", action="store_true")
+    ap.add_argument("--no-compression", action="store_true",
+                    help="skip the expected-attention profiles (scored rebuild, selection, op_eval on them)")
     ap.add_argument("--workload", choices=["filter", "mixed"], default="filter",
                     help="filter: the plain filter at scale (default); mixed: filter/map/join in one pass")
     ap.add_argument("--json-out", default=None)
@@ -90,9 +92,10 @@ def main():
     op = K.make_op(K.KVOP_FILTER, wl.suffix, synth.YES_ID, synth.NO_ID)
     stream = torch.cuda.current_stream()
 
-    def timed_eval(pool, r, handles, sel=None, steps=1, warmup=0):
-        """op_eval over the documents; returns (ms per step, logits, decisions)."""
-        idx, offs = lists[r]
+    def timed_eval(pool, r, handles, sel=None, steps=1, warmup=0, lst=None):
+        """op_eval over the documents (the seeded lists at r, or lst = (idx, offsets)); returns
+        (ms per step, logits, decisions)."""
+        idx, offs = lists[r] if lst is None else lst
         if sel is not None:
             # restrict to a contiguous range of documents [a, b)
             a, b = sel
@@ -163,6 +166,10 @@ def main():
     if proxy is not None:
         cascade = time_cascade(K, proxy, proxy_info, pool, hb, pooled, lists[1.0], op, bf16_out[1.0], n, args, dev,
                                stream)
+    compression = None
+    if not args.no_compression:
+        compression = time_compression(K, pool, hb, docs, toks, n, wl, t_build, timed_eval, bf16_out, args, dev,
+                                       stream)
     K.kvop_pool_destroy(pool)
     # ------------------------------------------------------------------ FP8 cache
     if not args.no_fp8:
@@ -260,6 +267,7 @@ def main():
         "bf16_plain_tuples_per_s": plain_value,
         "proxy": cascade,
         "per_r": per_r,
+        "compression": compression,
         "kv_build_bf16_s": result["kv_build_bf16_s"],
         "cpu_baseline": cpu,
     }
@@ -453,6 +461,54 @@ def bench_mixed(args, K, synth, dev):
             "profile_group0_ms": {"eager_mixed": prof_mixed, "separate_calls": prof_sep},
             "kv_build_s": t_build, "gemm_tiles": tiles}
     print(json.dumps(line), flush=True)
+
+
+def time_compression(K, pool, handles, docs, toks, n, wl, t_build, timed_eval, bf16_out, args, dev, stream):
+    """Compressed profiles by expected attention: the caches are rebuilt with scoring (timed
+    against the plain build), retained lists are selected at each r < 1 (timed), and the
+    filter runs over them; decisions and log-odds are compared with r = 1 next to those of
+    the seeded random lists at the same r."""
+    import torch
+    K.kvop_kv_release(pool, handles)
+    n_future = len(wl.suffix)
+    scores = torch.empty(int(docs.lengths.sum()), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    K.kvop_profile_start()
+    t0 = time.time()
+    hs = K.kvop_kv_build_scored(pool, toks, docs.offsets, n_future, scores)
+    torch.cuda.synchronize()
+    t_scored = time.time() - t0
+    prof = K.kvop_profile_stop()
+    log(f"kv_build with expected-attention scores: {t_scored:.2f} s (plain {t_build:.2f} s), "
+        f"scoring kernels {prof['ea_scores'][0]:.0f} ms")
+    lo1 = bf16_out[1.0][0][:, 0] - bf16_out[1.0][0][:, 1]
+    dec1 = bf16_out[1.0][1]
+    out = {"method": f"expected attention, future queries at L .. L+{n_future - 1}", "kv_build_s": t_build,
+           "kv_build_scored_s": t_scored, "scoring_kernels_ms": prof["ea_scores"][0], "per_r": {}}
+    for r in wl.r_grid:
+        if r == 1.0:
+            continue
+        total = sum(K.kvop_retained_count(r, int(L)) for L in docs.lengths)
+        idx = torch.empty(total, dtype=torch.int32, device=dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        io = K.kvop_ea_select(pool, scores, docs.offsets, r, idx)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sel_ms = e0.elapsed_time(e1)
+        ms, lg, dec = timed_eval(pool, r, hs, steps=max(1, args.steps // 2), warmup=args.warmup, lst=(idx, io))
+        lo = lg[:, 0] - lg[:, 1]
+        lo_rand = bf16_out[r][0][:, 0] - bf16_out[r][0][:, 1]
+        row = {"select_ms": sel_ms, "tuples_per_s": n / (ms / 1e3), "ms": ms,
+               "decision_agreement_vs_r1": float(np.mean(dec == dec1)),
+               "random_lists_decision_agreement_vs_r1": float(np.mean(bf16_out[r][1] == dec1)),
+               "mean_abs_logodds_change_vs_r1": float(np.mean(np.abs(lo - lo1))),
+               "random_lists_mean_abs_logodds_change_vs_r1": float(np.mean(np.abs(lo_rand - lo1)))}
+        out["per_r"][str(r)] = row
+        log(f"expected-attention lists r={r}: select {sel_ms:.2f} ms, op_eval {ms:.1f} ms; decisions agree with r=1 "
+            f"{row['decision_agreement_vs_r1']:.3f} (random lists {row['random_lists_decision_agreement_vs_r1']:.3f}), "
+            f"mean |dLO| {row['mean_abs_logodds_change_vs_r1']:.3f} (random {row['random_lists_mean_abs_logodds_change_vs_r1']:.3f})")
+    return out
 
 
 def autotune(K, model, rows_list, tag):

@@ -256,7 +256,9 @@ struct LayerPlan {
   SelGroup sel[kMaxSelGroups];
   // expected-attention scoring during prefill (off when ea_row_off is null)
   const int64_t* ea_row_off = nullptr;
-  int ea_nd = 0, ea_n_future = 0;
+  const int32_t* ea_order = nullptr;
+  const int32_t* ea_items = nullptr;
+  int ea_nd = 0, ea_n_items = 0, ea_n_future = 0;
   float* ea_e = nullptr;
   float* ea_acc = nullptr;
   void select_all() { n_groups = 1; sel[0] = SelGroup{rows, 1, 0}; }
@@ -281,8 +283,8 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   }
   if (lp.ea_row_off) {  // before the rotation: the statistics are of the pre-rotation queries
     ProfScope ps(PC_EA, st);
-    HIPTRY(ea_layer(dt, D, b.qkv, qc, H, Hkv, lp.ea_row_off, lp.ea_nd, lp.ea_n_future, m->cos_tab, m->sin_tab,
-                    lp.ea_e, lp.ea_acc, st));
+    HIPTRY(ea_layer(dt, D, b.qkv, qc, H, Hkv, lp.ea_row_off, lp.ea_order, lp.ea_nd, lp.ea_items, lp.ea_n_items,
+                    lp.ea_n_future, m->cos_tab, m->sin_tab, lp.ea_e, lp.ea_acc, st));
   }
   if (n_kvblocks > 0) {
     ProfScope ps(PC_ROPE_KV, st);
@@ -657,10 +659,27 @@ static kvop_status kv_build_impl(kvop_pool* p, const int32_t* tokens, const int6
     row_off[nd] = r;
     // longest key ranges first
     std::stable_sort(work.begin(), work.end(), [](const AttnWork& a, const AttnWork& b) { return a.n_a > b.n_a; });
+    // expected-attention workgroups: longest documents first
+    std::vector<int32_t> ea_ord(nd);
+    for (int i = 0; i < nd; i++) ea_ord[i] = i;
+    std::stable_sort(ea_ord.begin(), ea_ord.end(), [&](int32_t a, int32_t b2) {
+      return row_off[a + 1] - row_off[a] > row_off[b2 + 1] - row_off[b2];
+    });
+    // log-weight work items: key segments of at most 1024 rows, so that one long document
+    // spreads over several workgroups
+    std::vector<int32_t> ea_items;
+    for (int32_t dd : ea_ord) {
+      const int32_t Ld = (int32_t)(row_off[dd + 1] - row_off[dd]);
+      for (int32_t k0 = 0; k0 < Ld; k0 += 1024) {
+        ea_items.push_back(dd);
+        ea_items.push_back(k0);
+        ea_items.push_back(std::min<int32_t>(1024, Ld - k0));
+      }
+    }
     Mirror mir;
     size_t o_pos = mir.add(pos.size() * 4), o_blk = mir.add(blocks.size() * sizeof(KvBlock)),
            o_work = mir.add(work.size() * sizeof(AttnWork)), o_roff = mir.add(row_off.size() * 8),
-           o_inv = mir.add(rows * 4);
+           o_ord = mir.add(nd * 4), o_items = mir.add(ea_items.size() * 4), o_inv = mir.add(rows * 4);
     if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess) {
       rollback();
       return fail(KVOP_ENOMEM, "metadata staging");
@@ -669,6 +688,8 @@ static kvop_status kv_build_impl(kvop_pool* p, const int32_t* tokens, const int6
     memcpy(m->stage.p + o_blk, blocks.data(), blocks.size() * sizeof(KvBlock));
     memcpy(m->stage.p + o_work, work.data(), work.size() * sizeof(AttnWork));
     memcpy(m->stage.p + o_roff, row_off.data(), row_off.size() * 8);
+    memcpy(m->stage.p + o_ord, ea_ord.data(), nd * 4);
+    memcpy(m->stage.p + o_items, ea_items.data(), ea_items.size() * 4);
     char* md = (char*)m->meta.p;
     if (hipMemcpyAsync(md, m->stage.p, o_inv, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipEventRecord(m->stage.ev, st) != hipSuccess) {
@@ -699,6 +720,9 @@ static kvop_status kv_build_impl(kvop_pool* p, const int32_t* tokens, const int6
     float* ea_acc = ea_ws ? ea_ws + (size_t)ea_rows * H : nullptr;
     if (ea_ws) {
       lp.ea_row_off = (const int64_t*)(md + o_roff);
+      lp.ea_order = (const int32_t*)(md + o_ord);
+      lp.ea_items = (const int32_t*)(md + o_items);
+      lp.ea_n_items = (int)(ea_items.size() / 3);
       lp.ea_nd = nd;
       lp.ea_n_future = n_future;
       lp.ea_e = ea_ws;

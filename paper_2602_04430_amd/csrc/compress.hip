@@ -37,6 +37,20 @@ template <>
 __device__ inline float ld_f<float>(const float* p) { return *p; }
 template <>
 __device__ inline float ld_f<bf16_t>(const bf16_t* p) { return bf2f(*p); }
+// eight consecutive elements as floats (16-byte aligned for BF16, 32-byte for FP32)
+__device__ inline void ld8(const float* p, float (&x)[8]) {
+  const f32x4 a = *reinterpret_cast<const f32x4*>(p), b = *reinterpret_cast<const f32x4*>(p + 4);
+#pragma unroll
+  for (int i = 0; i < 4; i++) { x[i] = a[i]; x[i + 4] = b[i]; }
+}
+__device__ inline void ld8(const bf16_t* p, float (&x)[8]) {
+  const u32x4 v = *reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    x[2 * i] = __builtin_bit_cast(float, v[i] << 16);
+    x[2 * i + 1] = __builtin_bit_cast(float, v[i] & 0xffff0000u);
+  }
+}
 
 __device__ inline float block_sum(float v, float* red) {
   v = wave_sum(v);
@@ -58,15 +72,18 @@ __device__ inline float block_max(float v, float* red) {
 // ---------------------------------------------------------------- expected log-weights
 template <typename T, int D>
 __global__ __launch_bounds__(kEaThreads) void ea_logw_kernel(const T* __restrict__ qkv, int64_t ld, int H, int Hkv,
-                                                             const int64_t* __restrict__ row_off, int n_future,
+                                                             const int64_t* __restrict__ row_off,
+                                                             const int32_t* __restrict__ items, int n_future,
                                                              const float* __restrict__ cos_tab,
                                                              const float* __restrict__ sin_tab,
                                                              float* __restrict__ e_out) {
   constexpr int BR = D / 32, BC = D / 8, H2 = D / 2;
-  __shared__ float region[D * D > kEaChunk * D ? D * D : kEaChunk * D];  // covariance, or staged rows
+  __shared__ __attribute__((aligned(16))) float region[D * D > kEaChunk * D ? D * D : kEaChunk * D];  // S, or rows
   __shared__ float mu[D], mur[D], cb[H2], sb[H2];
-  __shared__ float red[4][kEaChunk];
-  const int doc = blockIdx.x / H, h = blockIdx.x % H, g = (h * Hkv) / H;
+  // work item: (document, first key, key count); the statistics always cover all the
+  // document's rows, the keys are this item's segment
+  const int32_t* it = items + 3 * (blockIdx.x / H);
+  const int doc = it[0], k_lo = it[1], k_hi = it[1] + it[2], h = blockIdx.x % H, g = (h * Hkv) / H;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t r0 = row_off[doc];
   const int L = (int)(row_off[doc + 1] - r0);
@@ -74,8 +91,9 @@ __global__ __launch_bounds__(kEaThreads) void ea_logw_kernel(const T* __restrict
   const T* Kp = qkv + r0 * ld + (int64_t)(H + g) * D;
   const int a0 = w * (D / 4) + (lane >> 3) * BR, b0 = (lane & 7) * BC;
 
-  // mean of the pre-rotation queries (each dimension's rows split over 256 / D threads)
-  {
+  // mean of the pre-rotation queries (FP32 path: a pass of its own, each dimension's rows
+  // split over 256 / D threads; the BF16 path sums the rows it stages for the covariance)
+  if constexpr (sizeof(T) == 4) {
     constexpr int SPLIT = kEaThreads / D;
     const int j = tid % D, part = tid / D;
     float s = 0.f;
@@ -90,33 +108,106 @@ __global__ __launch_bounds__(kEaThreads) void ea_logw_kernel(const T* __restrict
     }
     __syncthreads();
   }
-  // covariance (centred products), accumulated in the lane's block
-  float acc[BR][BC];
+  // covariance into region (float [D][D])
+  const float invL = 1.0f / (float)L;
+  if constexpr (sizeof(T) == 2) {
+    // BF16 queries: S = sum over rows of q q^T on MFMA (exact products, FP32 sums) from a
+    // transposed LDS tile (tile[d][r] = q[c0 + r][d], pitch 40 so that the 16 rows one
+    // fragment read touches fall on distinct banks), then S / L - mu mu^T
+    constexpr int NB = D / 16, PK = 40, NBW = NB * NB / 4, DG = D / 8;
+    static_assert(NBW * 4 == NB * NB, "output blocks per wavefront");
+    bf16_t* tile = reinterpret_cast<bf16_t*>(region);
+    f32x4 cacc[NBW];
 #pragma unroll
-  for (int a = 0; a < BR; a++)
+    for (int j = 0; j < NBW; j++) cacc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int sr = tid >> 3, sd = (tid & 7) * DG;   // staging: row, first dimension
+    float colsum[DG];
 #pragma unroll
-    for (int b = 0; b < BC; b++) acc[a][b] = 0.f;
-  for (int c0 = 0; c0 < L; c0 += kEaChunk) {
-    for (int e = tid; e < kEaChunk * D; e += kEaThreads) {
-      const int i = e / D, j = e % D;
-      region[e] = (c0 + i < L) ? ld_f(Q + (int64_t)(c0 + i) * ld + j) - mu[j] : 0.f;
+    for (int u = 0; u < DG; u++) colsum[u] = 0.f;
+    for (int c0 = 0; c0 < L; c0 += 32) {
+      bf16_t v[DG];
+      if (c0 + sr < L) {
+        const bf16_t* src = Q + (int64_t)(c0 + sr) * ld + sd;
+#pragma unroll
+        for (int u = 0; u < DG; u += 4) {
+          const u32x2 x = *reinterpret_cast<const u32x2*>(src + u);
+          v[u] = (bf16_t)(x[0] & 0xffff);
+          v[u + 1] = (bf16_t)(x[0] >> 16);
+          v[u + 2] = (bf16_t)(x[1] & 0xffff);
+          v[u + 3] = (bf16_t)(x[1] >> 16);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < DG; u++) v[u] = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < DG; u++) {
+        tile[(sd + u) * PK + sr] = v[u];
+        colsum[u] += bf2f(v[u]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NBW; j++) {
+        const int bi = w * NBW + j, br = bi / NB, bc = bi % NB;
+        const u32x4 fa = *reinterpret_cast<const u32x4*>(tile + (br * 16 + (lane & 15)) * PK + 8 * (lane >> 4));
+        const u32x4 fb = *reinterpret_cast<const u32x4*>(tile + (bc * 16 + (lane & 15)) * PK + 8 * (lane >> 4));
+        cacc[j] = mfma_bf16(__builtin_bit_cast(u16x8, fa), __builtin_bit_cast(u16x8, fb), cacc[j]);
+      }
+      __syncthreads();
+    }
+    // mean: the 32 staging threads of each dimension group add their column sums
+    float* part = region + D * PK / 2;   // past the tile (floats)
+#pragma unroll
+    for (int u = 0; u < DG; u++) part[sr * D + sd + u] = colsum[u];
+    __syncthreads();
+    if (tid < D) {
+      float t = 0.f;
+      for (int q = 0; q < 32; q++) t += part[q * D + tid];
+      mu[tid] = t * invL;
     }
     __syncthreads();
-    const int n = min(kEaChunk, L - c0);
+#pragma unroll
+    for (int j = 0; j < NBW; j++) {
+      const int bi = w * NBW + j, br = bi / NB, bc = bi % NB;
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int ra = br * 16 + 4 * (lane >> 4) + r, rb = bc * 16 + (lane & 15);
+        region[ra * D + rb] = cacc[j][r] * invL - mu[ra] * mu[rb];
+      }
+    }
+  } else {
+    // FP32 queries: centred products on the vector ALU, accumulated in the lane's block
+    float acc[BR][BC];
+#pragma unroll
+    for (int a = 0; a < BR; a++)
+#pragma unroll
+      for (int b = 0; b < BC; b++) acc[a][b] = 0.f;
+    for (int c0 = 0; c0 < L; c0 += kEaChunk) {
+      for (int e = tid; e < kEaChunk * D; e += kEaThreads) {
+        const int i = e / D, j = e % D;
+        region[e] = (c0 + i < L) ? ld_f(Q + (int64_t)(c0 + i) * ld + j) - mu[j] : 0.f;
+      }
+      __syncthreads();
+      const int n = min(kEaChunk, L - c0);
 #pragma unroll 1
-    for (int i = 0; i < n; i++) {
-      const float* x = region + i * D;
-      float xa[BR], xb[BC];
+      for (int i = 0; i < n; i++) {
+        const float* x = region + i * D;
+        float xa[BR], xb[BC];
 #pragma unroll
-      for (int a = 0; a < BR; a++) xa[a] = x[a0 + a];
+        for (int a = 0; a < BR; a++) xa[a] = x[a0 + a];
 #pragma unroll
-      for (int b = 0; b < BC; b++) xb[b] = x[b0 + b];
+        for (int b = 0; b < BC; b++) xb[b] = x[b0 + b];
 #pragma unroll
-      for (int a = 0; a < BR; a++)
+        for (int a = 0; a < BR; a++)
 #pragma unroll
-        for (int b = 0; b < BC; b++) acc[a][b] = fmaf(xa[a], xb[b], acc[a][b]);
+          for (int b = 0; b < BC; b++) acc[a][b] = fmaf(xa[a], xb[b], acc[a][b]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < BR; a++)
+#pragma unroll
+      for (int b = 0; b < BC; b++) region[(a0 + a) * D + b0 + b] = acc[a][b] * invL;
   }
   // averaged rotation over the future positions, and the rotated mean
   if (tid < H2) {
@@ -128,11 +219,6 @@ __global__ __launch_bounds__(kEaThreads) void ea_logw_kernel(const T* __restrict
     cb[tid] = c / (float)n_future;
     sb[tid] = s / (float)n_future;
   }
-  const float invL = 1.0f / (float)L;
-#pragma unroll
-  for (int a = 0; a < BR; a++)
-#pragma unroll
-    for (int b = 0; b < BC; b++) region[(a0 + a) * D + b0 + b] = acc[a][b] * invL;
   __syncthreads();
   if (tid < D) {
     const int j = tid % H2;
@@ -154,50 +240,69 @@ __global__ __launch_bounds__(kEaThreads) void ea_logw_kernel(const T* __restrict
     r1p[qb + H2] = sc * t10 + cc * t11;
   }
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < BR; a++)
-#pragma unroll
-    for (int b = 0; b < BC; b++) acc[a][b] = region[(a0 + a) * D + b0 + b];
   __syncthreads();  // covariance reads done before the region holds keys
-  // expected log-weight of every rotated key
+  // expected log-weight of every rotated key: one key per lane (256 per pass), its rotated
+  // values in registers; S_r rows are read from LDS by all lanes at once (broadcast), so no
+  // cross-lane reduction is needed
   const float inv_sqrt_d = rsqrtf((float)D), inv_2d = 0.5f / (float)D;
-  for (int c0 = 0; c0 < L; c0 += kEaChunk) {
-    for (int e = tid; e < kEaChunk * H2; e += kEaThreads) {
-      const int i = e / H2, j = e % H2, p = c0 + i;
-      float k1 = 0.f, k2 = 0.f;
-      if (p < L) {
-        const float x1 = ld_f(Kp + (int64_t)p * ld + j), x2 = ld_f(Kp + (int64_t)p * ld + j + H2);
-        const float cs = cos_tab[(int64_t)p * H2 + j], sn = sin_tab[(int64_t)p * H2 + j];
-        k1 = x1 * cs - x2 * sn;
-        k2 = x2 * cs + x1 * sn;
+  for (int c0 = k_lo; c0 < k_hi; c0 += kEaThreads) {
+    const int p = c0 + tid;
+    float k[D];
+    if (p < k_hi) {
+      const T* kr = Kp + (int64_t)p * ld;
+      const float* ct = cos_tab + (int64_t)p * H2;
+      const float* st = sin_tab + (int64_t)p * H2;
+#pragma unroll
+      for (int j = 0; j < H2; j += 8) {
+        float x1[8], x2[8];
+        ld8(kr + j, x1);
+        ld8(kr + j + H2, x2);
+#pragma unroll
+        for (int u = 0; u < 8; u += 4) {
+          const f32x4 cs = *reinterpret_cast<const f32x4*>(ct + j + u);
+          const f32x4 sn = *reinterpret_cast<const f32x4*>(st + j + u);
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            k[j + u + v] = x1[u + v] * cs[v] - x2[u + v] * sn[v];
+            k[j + u + v + H2] = x2[u + v] * cs[v] + x1[u + v] * sn[v];
+          }
+        }
       }
-      region[i * D + j] = k1;
-      region[i * D + j + H2] = k2;
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; j++) k[j] = 0.f;
     }
-    __syncthreads();
-    const int n = min(kEaChunk, L - c0);
+    float e = 0.f;
 #pragma unroll 1
-    for (int i = 0; i < n; i++) {
-      const float* k = region + i * D;
-      float kb[BC];
+    for (int blk = 0; blk < D / 8; blk++) {
+      float ka[8];
 #pragma unroll
-      for (int b = 0; b < BC; b++) kb[b] = k[b0 + b];
-      float part = 0.f;
+      for (int c = 0; c < D / 8; c++)   // blk is uniform: one branch taken, no indexed registers
+        if (c == blk) {
 #pragma unroll
-      for (int a = 0; a < BR; a++) {
-        float y = 0.f;
+          for (int u = 0; u < 8; u++) ka[u] = k[8 * c + u];
+        }
+      // the block's eight rows of S_r k as eight independent FMA chains (S_r rows: broadcast
+      // LDS reads)
+      const float* sr = region + 8 * blk * D;
+      float y[8];
 #pragma unroll
-        for (int b = 0; b < BC; b++) y = fmaf(acc[a][b], kb[b], y);
-        const float ka = k[a0 + a];
-        part = fmaf(ka, y * inv_2d, part);
-        if ((lane & 7) == 0) part = fmaf(ka, mur[a0 + a] * inv_sqrt_d, part);
+      for (int u = 0; u < 8; u++) y[u] = 0.f;
+#pragma unroll
+      for (int b = 0; b < D; b += 4) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const f32x4 s4 = *reinterpret_cast<const f32x4*>(sr + u * D + b);
+          y[u] = fmaf(s4[0], k[b], y[u]);
+          y[u] = fmaf(s4[1], k[b + 1], y[u]);
+          y[u] = fmaf(s4[2], k[b + 2], y[u]);
+          y[u] = fmaf(s4[3], k[b + 3], y[u]);
+        }
       }
-      part = wave_sum(part);
-      if (lane == 0) red[w][i] = part;
+#pragma unroll
+      for (int u = 0; u < 8; u++) e = fmaf(ka[u], fmaf(y[u], inv_2d, mur[8 * blk + u] * inv_sqrt_d), e);
     }
-    __syncthreads();
-    if (tid < n) e_out[(r0 + c0 + tid) * H + h] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    __syncthreads();
+    if (p < k_hi) e_out[(r0 + p) * H + h] = e;
   }
 }
 
@@ -205,11 +310,12 @@ __global__ __launch_bounds__(kEaThreads) void ea_logw_kernel(const T* __restrict
 template <typename T, int D>
 __global__ __launch_bounds__(kEaThreads) void ea_contrib_kernel(const T* __restrict__ qkv, int64_t ld, int H, int Hkv,
                                                                 const int64_t* __restrict__ row_off,
+                                                                const int32_t* __restrict__ order,
                                                                 const float* __restrict__ e_in,
                                                                 float* __restrict__ acc) {
   __shared__ float red[4];
   __shared__ float mx[64], zs[64];
-  const int doc = blockIdx.x / Hkv, g = blockIdx.x % Hkv, G = H / Hkv;
+  const int doc = order[blockIdx.x / Hkv], g = blockIdx.x % Hkv, G = H / Hkv;
   const int tid = threadIdx.x;
   const int64_t r0 = row_off[doc];
   const int L = (int)(row_off[doc + 1] - r0);
@@ -324,30 +430,31 @@ __global__ __launch_bounds__(kEaThreads) void ea_select_kernel(const float* __re
 }
 
 template <typename T, int D>
-hipError_t ea_layer_t(const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off, int nd, int n_future,
-                      const float* cos_tab, const float* sin_tab, float* e_ws, float* acc, hipStream_t st) {
-  hipLaunchKernelGGL((ea_logw_kernel<T, D>), dim3(nd * H), dim3(kEaThreads), 0, st, (const T*)qkv, ld, H, Hkv,
-                     row_off, n_future, cos_tab, sin_tab, e_ws);
+hipError_t ea_layer_t(const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off, const int32_t* order,
+                      int nd, const int32_t* items, int n_items, int n_future, const float* cos_tab,
+                      const float* sin_tab, float* e_ws, float* acc, hipStream_t st) {
+  hipLaunchKernelGGL((ea_logw_kernel<T, D>), dim3(n_items * H), dim3(kEaThreads), 0, st, (const T*)qkv, ld, H, Hkv,
+                     row_off, items, n_future, cos_tab, sin_tab, e_ws);
   hipLaunchKernelGGL((ea_contrib_kernel<T, D>), dim3(nd * Hkv), dim3(kEaThreads), 0, st, (const T*)qkv, ld, H, Hkv,
-                     row_off, (const float*)e_ws, acc);
+                     row_off, order, (const float*)e_ws, acc);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t ea_layer(int dt, int D, const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off, int nd,
-                    int n_future, const float* cos_tab, const float* sin_tab, float* e_ws, float* acc,
-                    hipStream_t st) {
+hipError_t ea_layer(int dt, int D, const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off,
+                    const int32_t* order, int nd, const int32_t* items, int n_items, int n_future,
+                    const float* cos_tab, const float* sin_tab, float* e_ws, float* acc, hipStream_t st) {
   if (nd <= 0) return hipSuccess;
   if (H % Hkv || H / Hkv > 64) return hipErrorInvalidValue;
   if (dt == DT_F32) {
-    if (D == 128) return ea_layer_t<float, 128>(qkv, ld, H, Hkv, row_off, nd, n_future, cos_tab, sin_tab, e_ws, acc, st);
-    if (D == 64) return ea_layer_t<float, 64>(qkv, ld, H, Hkv, row_off, nd, n_future, cos_tab, sin_tab, e_ws, acc, st);
-    if (D == 32) return ea_layer_t<float, 32>(qkv, ld, H, Hkv, row_off, nd, n_future, cos_tab, sin_tab, e_ws, acc, st);
+    if (D == 128) return ea_layer_t<float, 128>(qkv, ld, H, Hkv, row_off, order, nd, items, n_items, n_future, cos_tab, sin_tab, e_ws, acc, st);
+    if (D == 64) return ea_layer_t<float, 64>(qkv, ld, H, Hkv, row_off, order, nd, items, n_items, n_future, cos_tab, sin_tab, e_ws, acc, st);
+    if (D == 32) return ea_layer_t<float, 32>(qkv, ld, H, Hkv, row_off, order, nd, items, n_items, n_future, cos_tab, sin_tab, e_ws, acc, st);
   } else {
-    if (D == 128) return ea_layer_t<bf16_t, 128>(qkv, ld, H, Hkv, row_off, nd, n_future, cos_tab, sin_tab, e_ws, acc, st);
-    if (D == 64) return ea_layer_t<bf16_t, 64>(qkv, ld, H, Hkv, row_off, nd, n_future, cos_tab, sin_tab, e_ws, acc, st);
-    if (D == 32) return ea_layer_t<bf16_t, 32>(qkv, ld, H, Hkv, row_off, nd, n_future, cos_tab, sin_tab, e_ws, acc, st);
+    if (D == 128) return ea_layer_t<bf16_t, 128>(qkv, ld, H, Hkv, row_off, order, nd, items, n_items, n_future, cos_tab, sin_tab, e_ws, acc, st);
+    if (D == 64) return ea_layer_t<bf16_t, 64>(qkv, ld, H, Hkv, row_off, order, nd, items, n_items, n_future, cos_tab, sin_tab, e_ws, acc, st);
+    if (D == 32) return ea_layer_t<bf16_t, 32>(qkv, ld, H, Hkv, row_off, order, nd, items, n_items, n_future, cos_tab, sin_tab, e_ws, acc, st);
   }
   return hipErrorInvalidValue;
 }

@@ -85,10 +85,13 @@ int attention_get_impl();
 // One layer of a prefill chunk (rows of nd documents, chunk-relative row offsets row_off[nd+1],
 // qkv = the QKV projection before rotation, dt f32 or bf16, row stride ld): e_ws [rows][H]
 // receives every key's expected log-weight per query head, then acc [rows][Hkv] += the
-// layer's normalised contributions.  Documents need L + n_future <= the rotary table length.
-hipError_t ea_layer(int dt, int D, const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off, int nd,
-                    int n_future, const float* cos_tab, const float* sin_tab, float* e_ws, float* acc,
-                    hipStream_t st);
+// layer's normalised contributions.  order[nd]: the documents in the order their workgroups
+// are launched (longest first); items[n_items][3]: (document, first key, key count) segments
+// of the log-weight pass, longest documents first.  Documents need L + n_future <= the rotary
+// table length.
+hipError_t ea_layer(int dt, int D, const void* qkv, int64_t ld, int H, int Hkv, const int64_t* row_off,
+                    const int32_t* order, int nd, const int32_t* items, int n_items, int n_future,
+                    const float* cos_tab, const float* sin_tab, float* e_ws, float* acc, hipStream_t st);
 hipError_t ea_zero(float* p, int64_t n, hipStream_t st);
 // out[row] = sum over kv heads of acc[row][g]
 hipError_t ea_finish(const float* acc, int Hkv, int rows, float* out, hipStream_t st);

@@ -24,7 +24,9 @@ pytestmark = pytest.mark.gpu
 
 SHAPE128 = synth.ModelShape(n_layers=2, d_model=512, n_heads=4, n_kv_heads=2, head_dim=128, d_ffn=1024, vocab=512)
 SHAPE64 = synth.ModelShape(n_layers=2, d_model=256, n_heads=4, n_kv_heads=2, head_dim=64, d_ffn=512, vocab=512)
-LENGTHS = np.array([1, 2, 5, 16, 63, 64, 65, 130, 300], np.int64)
+# lengths: one row, ragged, and beyond 1024 rows (the log-weight pass splits a document's keys
+# into 1024-row segments that each recompute the document's statistics)
+LENGTHS = np.array([1, 2, 5, 16, 63, 64, 65, 130, 300, 1500, 2100], np.int64)
 
 
 def _docs(shape, seed, lengths=LENGTHS):

@@ -2,7 +2,9 @@
 5632, vocab 32000) over the 4096-document filter workload, evaluated in the launch
 configuration the benchmark times (all 4096 documents in one op_eval per r), with sampled
 documents checked one by one against the FP64 oracle for every (dtype, r).  Prints the
-error table: max-abs logit error and decisions outside the margin band.
+error table: max-abs logit error and decisions outside the margin band.  The BF16 build is
+the scored one (kvop_kv_build_scored: identical caches), and the expected-attention scores of
+sampled documents are checked against the oracle's emulation of the BF16 form.
 
 Bounds at this shape:
   FP32                 E = 1e-4   (as at the small shapes)
@@ -27,6 +29,7 @@ import pytest
 import torch
 
 from oracle import codecs
+from oracle import compress as oc
 from oracle import model as om
 from paper_2602_04430_amd import kvop as K
 from paper_2602_04430_amd import synth
@@ -41,6 +44,8 @@ E_BF16_FORM = 0.065     # GPU BF16 path vs the FP64 emulation of the BF16 form
 E_BF16 = 0.12          # GPU BF16 path vs the FP64 oracle
 E_SCALE = {("f32", "f32"): 1e-4, ("bf16", "bf16"): E_BF16, ("bf16", "fp8"): 0.35}
 E_FP8_FORMAT = 0.15      # GPU FP8 path vs the FP64 oracle of the FP8 cache format
+E_EA = 3e-2              # expected-attention row scores (BF16) vs the emulation of the BF16 form, relative
+EA_SAMPLE = [81, 100, 7]  # L = 64, 149, 123
 
 
 def _refs(m, wl, lists, store=None, tag="fp64"):
@@ -74,12 +79,16 @@ def fp8_format_refs(scale_setup):
 
 
 @pytest.fixture(scope="module")
-def bf16_form_refs(scale_setup):
-    s = scale_setup
-    w = synth.make_weights(s["shape"], 0)
+def bf16_form_model(scale_setup):
+    w = synth.make_weights(scale_setup["shape"], 0)
     wb = {k: codecs.bf16_round(v) if v.ndim == 2 else v for k, v in w.items()}
-    me = om.Model(s["shape"], wb, act=codecs.bf16_round)
-    return _refs(me, s["wl"], s["lists"], store=codecs.bf16_round, tag="bf16-form")
+    return om.Model(scale_setup["shape"], wb, act=codecs.bf16_round)
+
+
+@pytest.fixture(scope="module")
+def bf16_form_refs(scale_setup, bf16_form_model):
+    s = scale_setup
+    return _refs(bf16_form_model, s["wl"], s["lists"], store=codecs.bf16_round, tag="bf16-form")
 
 
 @pytest.mark.parametrize("compute,kv", [("bf16", "bf16"), ("bf16", "fp8"), ("f32", "f32")])
@@ -104,7 +113,13 @@ def test_scale_filter_sampled_parity(device, scale_setup, request, compute, kv):
     need = sum(K.kvop_doc_bytes(probe, int(L)) for L in sub.lengths)
     K.kvop_pool_destroy(probe)
     pool = K.kvop_pool_create(model, kvdt, need + (64 << 20))
-    handles = K.kvop_kv_build(pool, torch.from_numpy(sub.tokens).to(device), sub.offsets)
+    scored = compute == "bf16" and kv == "bf16"   # same caches, plus expected-attention scores
+    if scored:
+        scores = torch.empty(int(sub.lengths.sum()), dtype=torch.float32, device=device)
+        handles = K.kvop_kv_build_scored(pool, torch.from_numpy(sub.tokens).to(device), sub.offsets,
+                                         len(wl.suffix), scores)
+    else:
+        handles = K.kvop_kv_build(pool, torch.from_numpy(sub.tokens).to(device), sub.offsets)
     op = K.make_op(K.KVOP_FILTER, wl.suffix, synth.YES_ID, synth.NO_ID)
     E = E_SCALE[(compute, kv)]
     pos = {int(d): i for i, d in enumerate(sel)}
@@ -135,6 +150,18 @@ def test_scale_filter_sampled_parity(device, scale_setup, request, compute, kv):
             if qerr > qbound:
                 failures.append(line)
         say(line)
+    if scored:
+        # expected-attention scores of sampled documents from the same 4096-document build
+        me = request.getfixturevalue("bf16_form_model")
+        sc = scores.cpu().numpy().astype(np.float64)
+        for i in EA_SAMPLE:
+            ref = oc.ea_scores(me, docs.doc(i), len(wl.suffix))
+            got = sc[sub.offsets[pos[i]]:sub.offsets[pos[i] + 1]]
+            err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+            line = f"expected-attention scores, document {i} (L {len(ref)}): max relative error {err:.3g} (bound {E_EA})"
+            say(line)
+            if err > E_EA:
+                failures.append(line)
     K.kvop_pool_destroy(pool)
     K.kvop_model_destroy(model)
     assert not failures, failures
