@@ -168,8 +168,8 @@ def main():
                                stream)
     compression = None
     if not args.no_compression:
-        compression = time_compression(K, pool, hb, docs, toks, n, wl, t_build, timed_eval, bf16_out, args, dev,
-                                       stream)
+        compression = time_compression(K, pool, hb, op, lists[1.0], headline_ms, docs, toks, n, wl, t_build,
+                                       timed_eval, bf16_out, args, dev, stream)
     K.kvop_pool_destroy(pool)
     # ------------------------------------------------------------------ FP8 cache
     if not args.no_fp8:
@@ -463,7 +463,8 @@ def bench_mixed(args, K, synth, dev):
     print(json.dumps(line), flush=True)
 
 
-def time_compression(K, pool, handles, docs, toks, n, wl, t_build, timed_eval, bf16_out, args, dev, stream):
+def time_compression(K, pool, handles, op, lists1, ms1, docs, toks, n, wl, t_build, timed_eval, bf16_out, args,
+                     dev, stream):
     """Compressed profiles by expected attention: the caches are rebuilt with scoring (timed
     against the plain build), retained lists are selected at each r < 1 (timed), and the
     filter runs over them; decisions and log-odds are compared with r = 1 next to those of
@@ -485,6 +486,7 @@ def time_compression(K, pool, handles, docs, toks, n, wl, t_build, timed_eval, b
     dec1 = bf16_out[1.0][1]
     out = {"method": f"expected attention, future queries at L .. L+{n_future - 1}", "kv_build_s": t_build,
            "kv_build_scored_s": t_scored, "scoring_kernels_ms": prof["ea_scores"][0], "per_r": {}}
+    ea_lists, ea_lo = {}, {}
     for r in wl.r_grid:
         if r == 1.0:
             continue
@@ -498,6 +500,7 @@ def time_compression(K, pool, handles, docs, toks, n, wl, t_build, timed_eval, b
         sel_ms = e0.elapsed_time(e1)
         ms, lg, dec = timed_eval(pool, r, hs, steps=max(1, args.steps // 2), warmup=args.warmup, lst=(idx, io))
         lo = lg[:, 0] - lg[:, 1]
+        ea_lists[r], ea_lo[r] = (idx, io), lo
         lo_rand = bf16_out[r][0][:, 0] - bf16_out[r][0][:, 1]
         row = {"select_ms": sel_ms, "tuples_per_s": n / (ms / 1e3), "ms": ms,
                "decision_agreement_vs_r1": float(np.mean(dec == dec1)),
@@ -508,6 +511,66 @@ def time_compression(K, pool, handles, docs, toks, n, wl, t_build, timed_eval, b
         log(f"expected-attention lists r={r}: select {sel_ms:.2f} ms, op_eval {ms:.1f} ms; decisions agree with r=1 "
             f"{row['decision_agreement_vs_r1']:.3f} (random lists {row['random_lists_decision_agreement_vs_r1']:.3f}), "
             f"mean |dLO| {row['mean_abs_logodds_change_vs_r1']:.3f} (random {row['random_lists_mean_abs_logodds_change_vs_r1']:.3f})")
+    ms_r = {float(r): row["ms"] for r, row in out["per_r"].items()}
+    ms_r[1.0] = ms1
+    out["ladder"] = time_ladder(K, pool, hs, op, n, ea_lists, lists1, ea_lo, dec1, ms_r, args, dev)
+    return out
+
+
+LADDER = (0.1, 0.25, 0.5, 1.0)
+CALIB_DOCS = 512         # documents the thresholds are calibrated on
+CALIB_PRECISION = 0.99   # agreement with r = 1 required of an early stage's decisions
+
+
+def calibrate_theta(lo, ref_dec, target):
+    """Smallest symmetric threshold theta such that the items with |LO| > theta, decided by
+    sign, agree with the reference decisions on at least `target` of them (inf if none)."""
+    a = np.abs(lo)
+    order = np.argsort(-a, kind="stable")
+    agree = np.cumsum((lo[order] > 0).astype(np.int8) == ref_dec[order]) / np.arange(1, len(lo) + 1)
+    ok = np.flatnonzero(agree >= target)
+    if len(ok) == 0:
+        return float("inf")
+    k = int(ok[-1]) + 1                       # the top-k items by |LO| meet the target
+    return float(np.float32(a[order[k]] if k < len(a) else 0.0))
+
+
+def time_ladder(K, pool, handles, op, n, ea_lists, lists1, ea_lo, dec1, ms_r, args, dev):
+    """Filter cascade over the expected-attention profiles r = 0.1 -> 0.25 -> 0.5 -> 1, one
+    kvop_cascade_eval over all documents timed per step, under two threshold rules fixed on
+    the first documents: (a) the smallest thresholds whose decisions agree with r = 1 at the
+    target precision; (b) thresholds deciding half of the remaining items at each early stage
+    (a rule that exercises the forwarding whatever the model's quality).  Each is reported
+    with Eq. 4's cost predicted from the measured per-profile step times, so the executor's
+    own overhead is the difference."""
+    import torch
+    c = min(CALIB_DOCS, n)
+    rules = {"precision_%g" % CALIB_PRECISION:
+             [calibrate_theta(ea_lo[r][:c], dec1[:c], CALIB_PRECISION) for r in LADDER[:-1]] + [0.0],
+             "half_per_stage": [float(np.float32(np.quantile(np.abs(ea_lo[r][:c]), 0.5))) for r in LADDER[:-1]] + [0.0]}
+    lg = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    dec = torch.empty(n, dtype=torch.int8, device=dev)
+    stg = torch.empty(n, dtype=torch.int8, device=dev)
+    out = {"stages_r": list(LADDER), "calibration_docs": c}
+    for name, th in rules.items():
+        stages = [(r, t, -t, *(ea_lists[r] if r < 1.0 else lists1)) for r, t in zip(LADDER, th)]
+        for _ in range(args.warmup):
+            K.kvop_cascade_eval(pool, op, stages, handles, lg, dec, stg)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(args.steps):
+            proc = K.kvop_cascade_eval(pool, op, stages, handles, lg, dec, stg)
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) * 1e3 / args.steps
+        d = dec.cpu().numpy()
+        pred = sum(int(p) / n * ms_r[r] for p, r in zip(proc, LADDER))
+        row = {"theta": th, "tuples_per_s": n / (ms / 1e3), "ms": ms, "processed": [int(x) for x in proc],
+               "eq4_predicted_ms": pred, "decision_agreement_vs_r1": float(np.mean(d == dec1)),
+               "decision_agreement_vs_r1_outside_calibration": float(np.mean(d[c:] == dec1[c:])) if n > c else None}
+        out[name] = row
+        log(f"cascade ladder {LADDER} [{name}]: theta {[round(x, 3) for x in th]}, processed {row['processed']}, "
+            f"{ms:.1f} ms (Eq. 4 predicts {pred:.1f}), {row['tuples_per_s']:.0f} tuples/s, "
+            f"agreement with r=1 {row['decision_agreement_vs_r1']:.4f}")
     return out
 
 

@@ -216,6 +216,28 @@ kvop_status kvop_op_eval_select(kvop_pool* pool, const kvop_op* op, float r, con
                                 const int32_t* select_host, int32_t n_select, void* stream, float* logits_out_dev,
                                 int8_t* decision_out_dev);
 
+/* One stage of a filter cascade over cache profiles (Section 4.1): the same operator over the
+ * profile of retention r with its own thresholds.  The lists are as for kvop_op_eval. */
+typedef struct kvop_stage {
+  float r;
+  float theta_pos, theta_neg;       /* accept iff LO > theta_pos, reject iff LO < theta_neg */
+  const int32_t* idx_dev;           /* this profile's retained lists (device) */
+  const int64_t* idx_offsets_host;  /* int64[n_items (+1) or 2 n_items (+1) for joins] */
+} kvop_stage;
+
+/* A filter (or join) cascade over profiles of increasing cost (Section 4.1, Eqs. 1-3):
+ * every item starts unsure; stage i evaluates only the items all earlier stages left unsure
+ * (op->theta_* are replaced by the stage's thresholds) and accepts, rejects or leaves them
+ * unsure.  Outputs (device, one row per item): the logits and decision of the last stage
+ * that evaluated the item (decision -1 if it is still unsure after the last stage) and that
+ * stage's index in stage_out_dev (int8).  processed_host[n_stages] receives the number of
+ * items each stage evaluated (Eq. 4's unsure counts).  The call synchronises `stream`
+ * between stages (the unsure set is compacted on the host).  Errors: EINVAL (a map, no
+ * stages or more than 127, null pointers, a NaN threshold), and those of kvop_op_eval_select. */
+kvop_status kvop_cascade_eval(kvop_pool* pool, const kvop_op* op, const kvop_stage* stages, int32_t n_stages,
+                              const kvop_handle* handles_host, int32_t n_items, void* stream, float* logits_out_dev,
+                              int8_t* decision_out_dev, int8_t* stage_out_dev, int32_t* processed_host);
+
 /* ---- batching form -----------------------------------------------------------
  * Mixed operators in one pass (the batched execution of Section 5, "Execution-time
  * Batching", with variable-length work lists instead of padding): the items of

@@ -1174,6 +1174,47 @@ kvop_status kvop_op_eval_select(kvop_pool* p, const kvop_op* op, float r, const 
   return op_eval_impl(p, op, r, idx, idx_offsets, hs, n_items, select_host, n_select, stream, logits, decision, nullptr);
 }
 
+kvop_status kvop_cascade_eval(kvop_pool* p, const kvop_op* op, const kvop_stage* stages, int32_t n_stages,
+                              const kvop_handle* hs, int32_t n_items, void* stream, float* logits, int8_t* decision,
+                              int8_t* stage_out, int32_t* processed) {
+  if (!p || !op || !stages || n_stages < 1 || n_stages > 127 || n_items < 0 || !processed)
+    return fail(KVOP_EINVAL, "bad arguments");
+  if (op->kind != KVOP_FILTER && op->kind != KVOP_JOIN) return fail(KVOP_EINVAL, "a cascade runs filters or joins");
+  if (n_items > 0 && (!hs || !logits || !decision || !stage_out)) return fail(KVOP_EINVAL, "null output");
+  for (int i = 0; i < n_stages; i++) {
+    processed[i] = 0;
+    if (std::isnan(stages[i].theta_pos) || std::isnan(stages[i].theta_neg) || !stages[i].idx_offsets_host)
+      return fail(KVOP_EINVAL, "bad stage");
+  }
+  if (n_items == 0) return KVOP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> sel(n_items);
+  for (int t = 0; t < n_items; t++) sel[t] = t;               // every item starts unsure
+  std::vector<int8_t> dec(n_items, -1), stage_of(n_items, -1);
+  for (int i = 0; i < n_stages && !sel.empty(); i++) {
+    kvop_op o = *op;
+    o.theta_pos = stages[i].theta_pos;
+    o.theta_neg = stages[i].theta_neg;
+    kvop_status s = op_eval_impl(p, &o, stages[i].r, stages[i].idx_dev, stages[i].idx_offsets_host, hs, n_items,
+                                 sel.data(), (int32_t)sel.size(), stream, logits, decision, nullptr);
+    if (s != KVOP_OK) return s;
+    processed[i] = (int32_t)sel.size();
+    for (int32_t t : sel) stage_of[t] = (int8_t)i;
+    if (i + 1 == n_stages) break;
+    if (hipMemcpyAsync(dec.data(), decision, n_items, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(KVOP_EDEVICE, "decision readback");
+    std::vector<int32_t> next;
+    for (int32_t t : sel)
+      if (dec[t] == -1) next.push_back(t);                    // still unsure: on to the next stage
+    sel.swap(next);
+  }
+  if (hipMemcpyAsync(stage_out, stage_of.data(), n_items, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(KVOP_EDEVICE, "stage upload");
+  return KVOP_OK;
+}
+
 // ------------------------------------------------------------------ mixed operators (batching form)
 namespace {
 

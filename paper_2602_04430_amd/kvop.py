@@ -44,6 +44,11 @@ class kvop_op(C.Structure):
                 ("n_gen", C.c_int32), ("flags", C.c_uint32)]
 
 
+class kvop_stage(C.Structure):
+    _fields_ = [("r", C.c_float), ("theta_pos", C.c_float), ("theta_neg", C.c_float), ("idx_dev", C.c_void_p),
+                ("idx_offsets_host", C.POINTER(C.c_int64))]
+
+
 class kvop_mixed_op(C.Structure):
     _fields_ = [("op", kvop_op), ("logits_out_dev", C.c_void_p), ("decision_out_dev", C.c_void_p),
                 ("tokens_out_dev", C.c_void_p)]
@@ -71,6 +76,8 @@ _SIGS = {
                                   C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P]),
     "kvop_gemm_set_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "kvop_debug_read_cache": (C.c_int, [_P, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "kvop_cascade_eval": (C.c_int, [_P, C.POINTER(kvop_op), C.POINTER(kvop_stage), C.c_int32, _P, C.c_int32, _P, _P,
+                                    _P, _P, _P]),
     "kvop_op_eval_select": (C.c_int, [_P, C.POINTER(kvop_op), C.c_float, _P, _P, _P, C.c_int32, _P, C.c_int32, _P,
                                       _P, _P]),
     "kvop_proxy_create": (C.c_int, [C.c_int32, C.c_int32, _P, C.POINTER(_P)]),
@@ -298,6 +305,24 @@ def kvop_op_eval_select(pool, op: kvop_op, r: float, idx_dev, idx_offsets, handl
     n_items = len(h) // (2 if op.kind == KVOP_JOIN else 1)
     _check(lib().kvop_op_eval_select(pool, C.byref(op), float(r), _dptr(idx_dev), po, hp, n_items, sp, len(sel),
                                      _stream(stream), _dptr(logits_dev), _dptr(decision_dev)))
+
+
+def kvop_cascade_eval(pool, op: kvop_op, stages, handles, logits_dev, decision_dev, stage_dev,
+                      stream=None) -> np.ndarray:
+    """stages: sequence of (r, theta_pos, theta_neg, idx_dev, idx_offsets).  Returns the number
+    of items each stage evaluated."""
+    keep = []
+    arr = (kvop_stage * len(stages))()
+    for i, (r, tp, tn, idx_dev, offs) in enumerate(stages):
+        o = np.ascontiguousarray(np.asarray(offs, np.int64))
+        keep.append(o)
+        arr[i] = kvop_stage(float(r), float(tp), float(tn), _dptr(idx_dev), o.ctypes.data_as(C.POINTER(C.c_int64)))
+    h, hp = _host(handles, np.uint64)
+    n_items = len(h) // (2 if op.kind == KVOP_JOIN else 1)
+    processed = np.zeros(len(stages), np.int32)
+    _check(lib().kvop_cascade_eval(pool, C.byref(op), arr, len(stages), hp, n_items, _stream(stream), _dptr(logits_dev),
+                                   _dptr(decision_dev), _dptr(stage_dev), processed.ctypes.data_as(C.c_void_p)))
+    return processed
 
 
 def kvop_proxy_create(d_in: int, d_hidden: int, params_dev) -> C.c_void_p:
