@@ -361,6 +361,84 @@ kvop_status kvop_debug_fp8_to_bf16(const uint8_t* codes_dev, int32_t n, uint16_t
 kvop_status kvop_debug_read_cache(kvop_pool* pool, kvop_handle handle, int32_t layer, int32_t kv_head, int32_t kv,
                                   float* out_dev, void* stream);
 
+/* ---- plan optimizer over profiled log-odds (host only; no device work) -----------------
+ * Section 4.1: every logical filter is a cascade of candidate physical operators in cost
+ * order (here typically the same filter over cache profiles of increasing retention).  The
+ * choice of operators and their thresholds is relaxed -- pick factor sigmoid(s / tau), soft
+ * decision softmax([LO - theta+, theta- - LO, 0] / tau) -- so Eqs. 1-4 carry soft accept /
+ * reject / unsure values and a soft cost; Eqs. 5-7 count TP / FP / FN against the gold plan
+ * (every filter's most expensive operator; Section 4.2: a tuple passes iff every filter
+ * accepts it); Eqs. 8-9 give the Beta(1 + TP, 1 + FN) and Beta(1 + TP, 1 + FP) lower bounds
+ * l with P(X >= l) = alpha; Eqs. 10-13 give the loss cost / (|S| sum c) + beta ReLU(T_P -
+ * l_P) + beta ReLU(T_R - l_R), minimised by Adam (0.9, 0.999, 1e-8) while tau falls
+ * exponentially from tau0 to tau_end.  The plan is read at tau = 0: an operator is selected
+ * iff s > 0; thresholds with theta+ < theta- collapse to their midpoint.  A tuple still unsure
+ * after a filter's last selected operator is not accepted.
+ * Parameters are laid out per operator (s, theta+, theta-), filters in order; pick scores
+ * start at 0 and thresholds at +theta0 / -theta0.  All arrays are host memory owned by the
+ * caller.  Errors: EINVAL for empty or inconsistent problems (no filter, a filter without
+ * operators or with more than 64, a cost <= 0, non-finite log-odds, alpha outside (0, 1),
+ * targets outside [0, 1]) and bad options. */
+typedef struct kvop_plan_problem {
+  int32_t n_filters;             /* logical filters, 1..64 */
+  const int32_t* n_ops;          /* [n_filters] candidate operators of every filter, 1..64 */
+  const double* cost;            /* [n_total] per-tuple cost of every operator, > 0 */
+  const float* log_odds;         /* [n_total][n_tuples] profiled log-odds, operator-major */
+  const int8_t* gold;            /* [n_filters][n_tuples] 1 iff the filter's gold operator accepts */
+  int32_t n_tuples;              /* profiling sample size |S| >= 1 */
+  double target_recall, target_precision;  /* T_R, T_P in [0, 1] */
+  double alpha;                  /* credible level in (0, 1) */
+} kvop_plan_problem;
+
+typedef struct kvop_plan_opts {
+  int32_t steps;                 /* Adam steps >= 1 */
+  double lr;                     /* Adam step size > 0 */
+  double beta;                   /* constraint weight >= 0 */
+  double tau0, tau_end;          /* temperature at the first and the last step, tau0 >= tau_end > 0 */
+  double theta0;                 /* initial thresholds +theta0 / -theta0 */
+} kvop_plan_opts;
+
+typedef struct kvop_plan_report {
+  double tp, fp, fn;             /* Eqs. 5-7 of the discrete plan on the sample */
+  double recall_lb, precision_lb;  /* Eqs. 8-9 */
+  double cost_frac;              /* Eq. 10's cost term of the discrete plan */
+} kvop_plan_report;
+
+/* Optimise.  Outputs: params_out[3 n_total] (nullable) the final relaxed parameters;
+ * selected_out[n_total], theta_pos_out / theta_neg_out[n_total] the plan at tau = 0;
+ * loss_trace_out[steps] (nullable) the loss at every step before its update; report_out
+ * (nullable) the discrete plan evaluated on the sample. */
+kvop_status kvop_plan_optimize(const kvop_plan_problem* problem, const kvop_plan_opts* opts, double* params_out,
+                               int8_t* selected_out, float* theta_pos_out, float* theta_neg_out,
+                               double* loss_trace_out, kvop_plan_report* report_out);
+
+/* The relaxed loss at parameters params[3 n_total] and temperature tau > 0, and its exact
+ * gradient into grad_out[3 n_total] (nullable). */
+kvop_status kvop_plan_loss(const kvop_plan_problem* problem, const double* params, double tau, double beta,
+                           double* loss_out, double* grad_out);
+
+/* A discrete plan on the sample: report, and per operator the inter-operator selectivity
+ * (fraction of the sample it does not reject), the intra-operator selectivity (fraction it
+ * leaves unsure) -- both over the whole sample, as Section 4.2 defines them -- the tuples it
+ * processes in its cascade (0 if not selected), and per tuple whether the plan accepts it.
+ * Every output is nullable.  Decisions compare the FP32 log-odds with the FP32 thresholds,
+ * as kvop_op_eval does. */
+kvop_status kvop_plan_evaluate(const kvop_plan_problem* problem, const int8_t* selected, const float* theta_pos,
+                               const float* theta_neg, kvop_plan_report* report_out, double* sel_inter_out,
+                               double* sel_intra_out, int32_t* processed_out, int8_t* accept_out);
+
+/* Operator ordering (Section 4.2, Algorithm 1): n_ops (1..20) physical operators, impl[i] the
+ * logical operator (0..63) of operator i; running operator i costs cost[i] per pending tuple of
+ * its logical operator, then keeps the sel_intra[i] fraction of them pending and the
+ * sel_inter[i] fraction of every other logical operator's.  The subset dynamic programme
+ * keeps, per subset, the cheapest way to have run exactly it.  Writes the order (operator
+ * indices) and its cost for n_tuples initial tuples. */
+kvop_status kvop_plan_reorder(int32_t n_ops, const int32_t* impl, const double* cost, const double* sel_inter,
+                              const double* sel_intra, double n_tuples, int32_t* order_out, double* cost_out);
+
+/* Eqs. 8-9's bound: l with P(X >= l) = alpha for X ~ Beta(a, b); a, b > 0, alpha in (0, 1). */
+kvop_status kvop_beta_lower_bound(double a, double b, double alpha, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,11 @@ _SIGS = {
     "kvop_profile_num_classes": (C.c_int32, []),
     "kvop_profile_launches": (C.c_int32, [C.c_int32, _P, C.c_int32]),
     "kvop_profile_class_name": (C.c_char_p, [C.c_int32]),
+    "kvop_plan_optimize": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "kvop_plan_loss": (C.c_int, [_P, _P, C.c_double, C.c_double, _P, _P]),
+    "kvop_plan_evaluate": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "kvop_plan_reorder": (C.c_int, [C.c_int32, _P, _P, _P, _P, C.c_double, _P, _P]),
+    "kvop_beta_lower_bound": (C.c_int, [C.c_double, C.c_double, C.c_double, _P]),
 }
 _lib_handle = None
 
@@ -414,3 +419,90 @@ def kvop_tuning_export() -> str:
 
 def kvop_tuning_import(text: str) -> None:
     _check(lib().kvop_tuning_import(text.encode()))
+
+
+# ----------------------------------------------------------------------------- plan optimizer (host)
+
+class kvop_plan_problem(C.Structure):
+    _fields_ = [("n_filters", C.c_int32), ("n_ops", C.c_void_p), ("cost", C.c_void_p), ("log_odds", C.c_void_p),
+                ("gold", C.c_void_p), ("n_tuples", C.c_int32), ("target_recall", C.c_double),
+                ("target_precision", C.c_double), ("alpha", C.c_double)]
+
+
+class kvop_plan_opts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_double), ("beta", C.c_double), ("tau0", C.c_double),
+                ("tau_end", C.c_double), ("theta0", C.c_double)]
+
+
+class kvop_plan_report(C.Structure):
+    _fields_ = [("tp", C.c_double), ("fp", C.c_double), ("fn", C.c_double), ("recall_lb", C.c_double),
+                ("precision_lb", C.c_double), ("cost_frac", C.c_double)]
+
+
+class PlanProblem:
+    """Host arrays of a kvop_plan_problem kept alive with the struct.
+    log_odds: per filter [n_j, S]; cost: per filter [n_j]; gold: per filter [S] (0/1)."""
+
+    def __init__(self, log_odds, cost, gold, target_recall, target_precision, alpha):
+        self.n_ops = np.array([np.asarray(x).shape[0] for x in log_odds], np.int32)
+        self.lo = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float32) for x in log_odds]), np.float32)
+        self.cost = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float64) for c in cost]), np.float64)
+        self.gold = np.ascontiguousarray(np.stack([np.asarray(g, np.int8) for g in gold]), np.int8)
+        self.n_total = int(self.n_ops.sum())
+        self.s = kvop_plan_problem(len(self.n_ops), self.n_ops.ctypes.data, self.cost.ctypes.data,
+                                   self.lo.ctypes.data, self.gold.ctypes.data, int(self.lo.shape[1]),
+                                   float(target_recall), float(target_precision), float(alpha))
+
+
+def _report(r: kvop_plan_report) -> dict:
+    return {k: getattr(r, k) for k, _ in kvop_plan_report._fields_}
+
+
+def kvop_plan_optimize(pb: PlanProblem, steps=300, lr=0.05, beta=10.0, tau0=1.0, tau_end=0.02, theta0=1.0) -> dict:
+    o = kvop_plan_opts(int(steps), float(lr), float(beta), float(tau0), float(tau_end), float(theta0))
+    n = pb.n_total
+    params = np.zeros(3 * n, np.float64)
+    sel = np.zeros(n, np.int8)
+    tp, tn = np.zeros(n, np.float32), np.zeros(n, np.float32)
+    trace = np.zeros(int(steps), np.float64)
+    rep = kvop_plan_report()
+    _check(lib().kvop_plan_optimize(C.byref(pb.s), C.byref(o), params.ctypes.data, sel.ctypes.data, tp.ctypes.data,
+                                    tn.ctypes.data, trace.ctypes.data, C.byref(rep)))
+    return {"params": params, "selected": sel, "theta_pos": tp, "theta_neg": tn, "trace": trace,
+            "report": _report(rep)}
+
+
+def kvop_plan_loss(pb: PlanProblem, params, tau: float, beta: float):
+    p = np.ascontiguousarray(params, np.float64)
+    g = np.zeros(3 * pb.n_total, np.float64)
+    out = C.c_double()
+    _check(lib().kvop_plan_loss(C.byref(pb.s), p.ctypes.data, float(tau), float(beta), C.byref(out), g.ctypes.data))
+    return out.value, g
+
+
+def kvop_plan_evaluate(pb: PlanProblem, selected, theta_pos, theta_neg) -> dict:
+    sel = np.ascontiguousarray(selected, np.int8)
+    tp, tn = np.ascontiguousarray(theta_pos, np.float32), np.ascontiguousarray(theta_neg, np.float32)
+    n, S = pb.n_total, pb.lo.shape[1]
+    inter, intra = np.zeros(n), np.zeros(n)
+    proc, acc = np.zeros(n, np.int32), np.zeros(S, np.int8)
+    rep = kvop_plan_report()
+    _check(lib().kvop_plan_evaluate(C.byref(pb.s), sel.ctypes.data, tp.ctypes.data, tn.ctypes.data, C.byref(rep),
+                                    inter.ctypes.data, intra.ctypes.data, proc.ctypes.data, acc.ctypes.data))
+    return {"report": _report(rep), "sel_inter": inter, "sel_intra": intra, "processed": proc, "accept": acc}
+
+
+def kvop_plan_reorder(impl, cost, sel_inter, sel_intra, n_tuples: float):
+    im = np.ascontiguousarray(impl, np.int32)
+    c, si, sa = (np.ascontiguousarray(x, np.float64) for x in (cost, sel_inter, sel_intra))
+    order = np.zeros(len(im), np.int32)
+    out = C.c_double()
+    _check(lib().kvop_plan_reorder(len(im), im.ctypes.data, c.ctypes.data, si.ctypes.data, sa.ctypes.data,
+                                   float(n_tuples), order.ctypes.data, C.byref(out)))
+    return order, out.value
+
+
+def kvop_beta_lower_bound(a: float, b: float, alpha: float) -> float:
+    out = C.c_double()
+    _check(lib().kvop_beta_lower_bound(float(a), float(b), float(alpha), C.byref(out)))
+    return out.value
