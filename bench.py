@@ -58,6 +58,7 @@ def main():
                     help="skip the expected-attention profiles (scored rebuild, selection, op_eval on them)")
     ap.add_argument("--workload", choices=["filter", "mixed"], default="filter",
                     help="filter: the plain filter at scale (default); mixed: filter/map/join in one pass")
+    ap.add_argument("--no-padded", action="store_true", help="skip the padded-batching ablation")
     ap.add_argument("--json-out", default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -156,6 +157,9 @@ def main():
         bf16_out[r] = (lg, dec)
         log(f"BF16 r={r}: {ms:.1f} ms/step, {n / (ms / 1e3):.0f} tuples/s")
     headline_ms = per_r["1.0"]["ms"]
+    padded = None
+    if not args.no_padded:
+        padded = time_padded(K, synth, pool, hb, lists, docs, wl, shape, per_r, args, dev)
     # per-kernel timing inside one r = 1 op_eval
     K.kvop_profile_start()
     timed_eval(pool, 1.0, hb, steps=1)
@@ -268,6 +272,7 @@ def main():
         "proxy": cascade,
         "per_r": per_r,
         "compression": compression,
+        "padded_batching": padded,
         "kv_build_bf16_s": result["kv_build_bf16_s"],
         "cpu_baseline": cpu,
     }
@@ -463,6 +468,60 @@ def bench_mixed(args, K, synth, dev):
     print(json.dumps(line), flush=True)
 
 
+PAD_BUDGET = 32 << 30    # bytes of padded cache one batch may hold (the padded form's batch rule)
+
+
+def time_padded(K, synth, pool, handles, lists, docs, wl, shape, per_r, args, dev):
+    """Padded batching as an ablation (KVOP_FLAG_PADDED: every item's attention runs over its
+    batch's largest key count).  Two forms per r: one batch of all documents (padding alone),
+    and batches formed in input order as the largest that keep batch size x padded length
+    within PAD_BUDGET of cache (padding plus the smaller batches it forces); each against the
+    variable-length rate of the same r."""
+    import torch
+    n = len(docs.lengths)
+    row_bytes = shape.n_layers * 2 * shape.n_kv_heads * shape.head_dim * 2
+    op = K.make_op(K.KVOP_FILTER, wl.suffix, synth.YES_ID, synth.NO_ID, flags=K.KVOP_FLAG_PADDED)
+    out = {"budget_bytes": PAD_BUDGET, "per_r": {}}
+    lg = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    dec = torch.empty(n, dtype=torch.int8, device=dev)
+    for r in wl.r_grid:
+        idx, offs = lists[r]
+        k = np.diff(offs)
+        batches, a = [], 0
+        while a < n:
+            b, kmax = a + 1, int(k[a])
+            while b < n and (b + 1 - a) * max(kmax, int(k[b])) * row_bytes <= PAD_BUDGET:
+                kmax = max(kmax, int(k[b]))
+                b += 1
+            batches.append((a, b))
+            a = b
+
+        def run(bs):
+            for a, b in bs:
+                sub = idx[int(offs[a]):int(offs[b])]
+                K.kvop_op_eval(pool, op, r, sub, offs[a:b + 1] - offs[a], handles[a:b], lg[a:b], dec[a:b])
+
+        row = {"varlen_ms": per_r[str(r)]["ms"], "real_keys": int(k.sum())}
+        for name, bs in (("one_batch", [(0, n)]), ("budget_batches", batches)):
+            run(bs)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            for _ in range(max(1, args.steps // 2)):
+                run(bs)
+            torch.cuda.synchronize()
+            ms = (time.time() - t0) * 1e3 / max(1, args.steps // 2)
+            padded_keys = sum((b - a) * int(k[a:b].max()) for a, b in bs)
+            row[name] = {"batches": len(bs), "ms": ms, "tuples_per_s": n / (ms / 1e3),
+                         "padded_keys_over_real": padded_keys / int(k.sum()),
+                         "varlen_speedup": ms / per_r[str(r)]["ms"]}
+        out["per_r"][str(r)] = row
+        log(f"padded r={r}: one batch {row['one_batch']['ms']:.1f} ms "
+            f"(keys x{row['one_batch']['padded_keys_over_real']:.2f}), {len(batches)} budget batches "
+            f"{row['budget_batches']['ms']:.1f} ms (keys x{row['budget_batches']['padded_keys_over_real']:.2f}); "
+            f"varlen {row['varlen_ms']:.1f} ms")
+    return out
+
+
 def time_compression(K, pool, handles, op, lists1, ms1, docs, toks, n, wl, t_build, timed_eval, bf16_out, args,
                      dev, stream):
     """Compressed profiles by expected attention: the caches are rebuilt with scoring (timed
@@ -513,6 +572,7 @@ def time_compression(K, pool, handles, op, lists1, ms1, docs, toks, n, wl, t_bui
             f"mean |dLO| {row['mean_abs_logodds_change_vs_r1']:.3f} (random {row['random_lists_mean_abs_logodds_change_vs_r1']:.3f})")
     ms_r = {float(r): row["ms"] for r, row in out["per_r"].items()}
     ms_r[1.0] = ms1
+    ea_lo[1.0] = lo1
     out["ladder"] = time_ladder(K, pool, hs, op, n, ea_lists, lists1, ea_lo, dec1, ms_r, args, dev)
     return out
 
@@ -571,7 +631,55 @@ def time_ladder(K, pool, handles, op, n, ea_lists, lists1, ea_lo, dec1, ms_r, ar
         log(f"cascade ladder {LADDER} [{name}]: theta {[round(x, 3) for x in th]}, processed {row['processed']}, "
             f"{ms:.1f} ms (Eq. 4 predicts {pred:.1f}), {row['tuples_per_s']:.0f} tuples/s, "
             f"agreement with r=1 {row['decision_agreement_vs_r1']:.4f}")
+    out["optimized"] = optimized_plan(K, pool, handles, op, n, ea_lists, lists1, ea_lo, dec1, ms_r, args, dev, c)
     return out
+
+
+PLAN_TARGETS = (0.9, 0.9, 0.95)   # recall target, precision target, credible level
+
+
+def optimized_plan(K, pool, handles, op, n, ea_lists, lists1, ea_lo, dec1, ms_r, args, dev, c):
+    """The optimizer (kvop_plan_optimize) on the profiled log-odds of the first c documents
+    at every profile of the ladder, costs = measured per-tuple times, gold = the r = 1
+    decisions; its plan then runs over all documents through kvop_cascade_eval, and the
+    realised recall and precision against r = 1 are reported beside the sample's bounds."""
+    import torch
+    lo = np.stack([ea_lo[r][:c] for r in LADDER[:-1]] + [ea_lo[1.0][:c]])
+    cost = np.array([ms_r[r] / n for r in LADDER])
+    gold = (dec1[:c] == 1).astype(np.int8)
+    pb = K.PlanProblem([lo], [cost], [gold], *PLAN_TARGETS)
+    t0 = time.time()
+    res = K.kvop_plan_optimize(pb, steps=300)
+    opt_ms = (time.time() - t0) * 1e3
+    sel = [i for i in range(len(LADDER)) if res["selected"][i]]
+    rep = res["report"]
+    row = {"targets": {"recall": PLAN_TARGETS[0], "precision": PLAN_TARGETS[1], "alpha": PLAN_TARGETS[2]},
+           "sample_docs": c, "optimizer_ms": opt_ms, "selected_r": [LADDER[i] for i in sel],
+           "theta_pos": [float(res["theta_pos"][i]) for i in sel], "theta_neg": [float(res["theta_neg"][i]) for i in sel],
+           "sample_report": rep}
+    if sel:
+        stages = [(LADDER[i], float(res["theta_pos"][i]), float(res["theta_neg"][i]),
+                   *(ea_lists[LADDER[i]] if LADDER[i] < 1.0 else lists1)) for i in sel]
+        lg = torch.empty(n, 2, dtype=torch.float32, device=dev)
+        dec = torch.empty(n, dtype=torch.int8, device=dev)
+        stg = torch.empty(n, dtype=torch.int8, device=dev)
+        K.kvop_cascade_eval(pool, op, stages, handles, lg, dec, stg)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for _ in range(args.steps):
+            proc = K.kvop_cascade_eval(pool, op, stages, handles, lg, dec, stg)
+        torch.cuda.synchronize()
+        ms = (time.time() - t0) * 1e3 / args.steps
+        acc = dec.cpu().numpy() == 1
+        g = dec1 == 1
+        tp = int(np.sum(acc & g))
+        row.update({"tuples_per_s": n / (ms / 1e3), "ms": ms, "processed": [int(x) for x in proc],
+                    "recall_vs_r1": tp / max(1, int(g.sum())), "precision_vs_r1": tp / max(1, int(acc.sum()))})
+    log(f"optimized plan: r {row['selected_r']}, theta+ {[round(x, 3) for x in row['theta_pos']]}, "
+        f"sample bounds R {rep['recall_lb']:.3f} P {rep['precision_lb']:.3f}, cost {rep['cost_frac']:.3f}; "
+        f"optimizer {opt_ms:.0f} ms; all docs: {row.get('tuples_per_s', 0):.0f} tuples/s, "
+        f"recall {row.get('recall_vs_r1', 0):.4f} precision {row.get('precision_vs_r1', 0):.4f}")
+    return row
 
 
 def autotune(K, model, rows_list, tag):

@@ -178,6 +178,15 @@ typedef struct kvop_op {
 /* Skip the check that each list holds exactly k(r, L) rows (the caller may then
  * pass any valid sorted list; r is only range-checked). */
 #define KVOP_FLAG_ANY_COUNT 1u
+/* Padded batching, the form Section 5 ("Execution-time Batching") describes, kept as an
+ * ablation of the variable-length work lists: every item's attention runs over the largest
+ * cached key count of its wave (a join: of A and B together); the keys past the item's own
+ * are loaded (its own retained rows again, cyclically), multiplied and masked, so results
+ * equal the unpadded call's exactly while the work is that of a padded batch.  kvop_op_eval,
+ * kvop_op_eval_select and kvop_cascade_eval honour it (kvop_mixed_eval ignores it); only the
+ * direct-load attention kernels implement it: EINVAL for FP32 compute, an FP32 cache,
+ * head_dim other than 64/128 or attention variant -1. */
+#define KVOP_FLAG_PADDED 2u
 
 /* Online execution (Section 5, "Online"): evaluate one operator over n_items
  * items.  A filter/map item is one document; a join item is an ordered pair of

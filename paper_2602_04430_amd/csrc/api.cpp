@@ -860,6 +860,10 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
   const bool join = kind == KVOP_JOIN;
   const int per = join ? 2 : 1;
   if (select && kind == KVOP_MAP) return fail(KVOP_EINVAL, "item selection applies to filters and joins");
+  const bool padded = (op->flags & KVOP_FLAG_PADDED) != 0;
+  if (padded && !attention_is_dma(m->dt, p->kvdt, m->cfg.head_dim))
+    return fail(KVOP_EINVAL, "padded batching needs the direct-load attention kernels (BF16 compute, BF16 or FP8 "
+                             "cache, head_dim 64 or 128, attention variant >= 0)");
   // evaluated items (all, or the selection) and their lists: list lidx[i*per + j]
   const int n_eval = select ? n_select : n_items;
   std::vector<int32_t> ids(n_eval);
@@ -959,6 +963,11 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     }
     std::stable_sort(work.begin(), work.end(),
                      [](const AttnWork& a, const AttnWork& b) { return a.n_a + a.n_b > b.n_a + b.n_b; });
+    if (padded) {
+      // every item of the wave iterates over the wave's largest key count (padding of A)
+      const int kmax = work.empty() ? 0 : work.front().n_a + work.front().n_b;
+      for (AttnWork& w : work) w.pad_a = kmax - w.n_b;
+    }
     // map decode: work items with one query position against (retained rows + own rows)
     std::vector<AttnWork> dwork;
     std::vector<int32_t> own_src, own_dst;
@@ -978,6 +987,11 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
         w.own_row0 = b * rows_per_item;
         w.own_pos0 = A->L;
         dwork.push_back(w);
+      }
+      if (padded) {
+        int kmax = 0;
+        for (const AttnWork& w : dwork) kmax = std::max(kmax, w.n_a);
+        for (AttnWork& w : dwork) w.pad_a = kmax;
       }
       own_src.resize(rows);
       own_dst.resize(rows);

@@ -472,10 +472,13 @@ static int g_attn_impl = 2;  // direct-load tiles, 32 keys, 3 stages (the fastes
 void attention_set_impl(int impl) { g_attn_impl = impl; }
 int attention_get_impl() { return g_attn_impl; }
 
+bool attention_is_dma(int cdt, int kvdt, int D) {
+  return g_attn_impl >= 0 && cdt == DT_BF16 && (kvdt == DT_BF16 || kvdt == DT_FP8) && (D == 64 || D == 128);
+}
+
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st) {
   if (a.n_work <= 0) return hipSuccess;
-  if (g_attn_impl >= 0 && cdt == DT_BF16 && (kvdt == DT_BF16 || kvdt == DT_FP8) && (D == 64 || D == 128))
-    return attention_dma(kvdt, D, g_attn_impl, a, st);
+  if (attention_is_dma(cdt, kvdt, D)) return attention_dma(kvdt, D, g_attn_impl, a, st);
   if (a.counter && a.persistent_wgs < 1) return hipErrorInvalidValue;
   if (a.G * a.Pmax > 64 || a.G < 1 || a.Pmax < 1) return hipErrorInvalidValue;
   if (cdt == DT_F32) {

@@ -132,6 +132,7 @@ struct __attribute__((aligned(8))) DmaSrc {
   const float* ksc;     // FP8 block scales (per 16 rows) or null
   const float* vsc;
   int n, clampL, pos_add;
+  int npad;             // keys iterated (>= n when padded, else n); keys past n are masked
 };
 static_assert(sizeof(DmaSrc) <= 64, "descriptor slot");
 
@@ -174,8 +175,9 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
   // ---- key sources: 0 = document A, 1 = document B, 2 = own rows.  Three separate
   // variables selected field by field (a dynamically indexed local array would live in
   // scratch memory, and a scratch load waits behind every tile load in flight).
-  auto init_doc = [&](DmaSrc& s, int64_t off, int L, int64_t il, int n, int pos_add) {
+  auto init_doc = [&](DmaSrc& s, int64_t off, int L, int64_t il, int n, int pos_add, int pad) {
     s.n = n;
+    s.npad = n > 0 ? max(n, pad) : 0;
     s.clampL = max(L, 1);
     s.pos_add = pos_add;
     s.idx = il >= 0 ? a.idx + il : nullptr;
@@ -197,11 +199,12 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
     }
   };
   DmaSrc src0, src1, src2;
-  init_doc(src0, w.off_a, w.L_a, w.idx_a, w.n_a, 0);
-  init_doc(src1, w.off_b, w.L_b, w.idx_b, w.n_b, w.L_a);
+  init_doc(src0, w.off_a, w.L_a, w.idx_a, w.n_a, 0, w.pad_a);
+  init_doc(src1, w.off_b, w.L_b, w.idx_b, w.n_b, w.L_a, 0);
   {
     DmaSrc& s = src2;
     s.n = w.n_own;
+    s.npad = w.n_own;
     s.clampL = max(w.n_own, 1);
     s.pos_add = w.own_pos0;
     s.idx = nullptr;
@@ -211,7 +214,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
     s.k = ob + (int64_t)(a.own_kcol + h * D) * 2;
     s.v = ob + (int64_t)(a.own_vcol + h * D) * 2;
   }
-  const int TA = (src0.n + KT - 1) / KT, TB = (src1.n + KT - 1) / KT;
+  const int TA = (src0.npad + KT - 1) / KT, TB = (src1.npad + KT - 1) / KT;
   const int TO = (src2.n + C::KTO - 1) / C::KTO;
   // The three descriptors go to LDS once; the issuing and the computing side each keep a
   // register copy of the current source and reload it from LDS when their tile index
@@ -251,7 +254,10 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
     int sidx, t0;
     tile_src(ti, sidx, t0);
     const DmaSrc& s = issue_src(sidx);
-    const int32_t* g = s.idx ? s.idx + min(t0 + lane, s.n - 1) : dummy;
+    // a padded tile (past the source's keys) loads the source's rows again from the start
+    // of the list, cyclically: real rows, so the padded keys cost loads and multiplies
+    const int tl = t0 < s.n ? t0 : t0 % s.n;
+    const int32_t* g = s.idx ? s.idx + min(tl + lane, s.n - 1) : dummy;
     __builtin_amdgcn_global_load_lds(g, (lds_void_t*)(ring + (ti % (NS + 1)) * 64), 4, 0, 0);
   };
   // chunk loads of tile ti into stage st, then one metadata load per wavefront (key =
@@ -261,6 +267,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
     int sidx, t0;
     tile_src(ti, sidx, t0);
     const DmaSrc& s = issue_src(sidx);
+    const int tl = t0 < s.n ? t0 : t0 % s.n;   // as in issue_rows
     const int* rws = ring + (ti % (NS + 1)) * 64;
     uint8_t* sb = smem + st * C::STAGE;
     const bool own = sidx == 2;
@@ -271,7 +278,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
       const bool is_v = j >= C::NR;
       const int f = 256 * jr + tid;              // chunk index inside the part
       const int rr = f / ch, slot = f % ch;
-      const int t = min(t0 + rr, s.n - 1);
+      const int t = min(tl + rr, s.n - 1);
       const int row = min(max(s.idx ? rws[rr] : t, 0), s.clampL - 1);
       int sw;
       if (own) sw = is_v ? swz_v<C::CHO>(rr) : swz_k<C::CHO>(rr);
@@ -282,7 +289,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
       __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 16, 0, 0);
     }
     float* meta = reinterpret_cast<float*>(sb + 2 * C::REGION);
-    const int row = min(max(s.idx ? rws[lane] : min(t0 + lane, s.n - 1), 0), s.clampL - 1);
+    const int row = min(max(s.idx ? rws[lane] : min(tl + lane, s.n - 1), 0), s.clampL - 1);
     const void* g = dummy;
     if (wave == 0 && s.ksc) g = s.ksc + (row >> 4);
     if (wave == 1 && s.vsc) g = s.vsc + (row >> 4);

@@ -50,6 +50,8 @@ struct AttnWork {
   int32_t own_row0;   // first own row (suffix/generated keys) in the own-row buffer
   int32_t n_own;      // own keys; own key j sits at position own_pos0 + j
   int32_t own_pos0;
+  int32_t pad_a;      // padded batching: keys of A iterated (>= n_a; keys past n_a are loaded,
+                      // multiplied and masked); 0 = n_a.  Direct-load kernels only.
 };
 
 struct AttnArgs {
@@ -77,6 +79,8 @@ hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st
 hipError_t attention_dma(int kvdt, int D, int variant, const AttnArgs& a, hipStream_t st);
 // FP8 (E4M3) codes -> BF16 bits with the conversion the direct-load kernels use (n % 8 == 0)
 hipError_t fp8_widen(const uint8_t* codes, uint16_t* out, int n, hipStream_t st);
+// whether attention() runs the direct-load kernels for this combination (they alone honour pad_a)
+bool attention_is_dma(int cdt, int kvdt, int D);
 // attention kernel used by attention(): -1 = register-staged, else the attention_dma variant
 void attention_set_impl(int impl);
 int attention_get_impl();

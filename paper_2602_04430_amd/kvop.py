@@ -21,6 +21,7 @@ KVOP_F32, KVOP_BF16 = 0, 1
 KVOP_KV_F32, KVOP_KV_BF16, KVOP_KV_FP8 = 0, 1, 2
 KVOP_FILTER, KVOP_MAP, KVOP_JOIN = 0, 1, 2
 KVOP_FLAG_ANY_COUNT = 1
+KVOP_FLAG_PADDED = 2
 KVOP_MIXED_PERSISTENT, KVOP_MIXED_GRAPH = 1, 2
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EBADHANDLE", 4: "EDEVICE"}
 
