@@ -301,6 +301,7 @@ def main():
 
 WAVE_ROWS = 32768            # suffix rows per wave in the mixed bench
 DEFAULT_WAVE_ROWS = 131072   # the library's default
+SMALL_WAVE_ROWS = 2048       # launch-bound regime of the mixed bench
 
 
 def compare(acc, ref, out):
@@ -365,6 +366,7 @@ def bench_mixed(args, K, synth, dev):
             for k in t_mode if k != "graph_persistent"}
     t_build = 0.0
     n_items = 0
+    small = {"wave_rows": SMALL_WAVE_ROWS, "group": 0, "items_per_s": {}, "differences": {}}
     # waves of WAVE_ROWS suffix rows: each group then runs several full waves, so the
     # captured graph is replayed (the first wave and a partial last wave run directly)
     K.kvop_set_wave_rows(WAVE_ROWS)
@@ -438,6 +440,21 @@ def bench_mixed(args, K, synth, dev):
             K.kvop_op_eval(pool, opj, 1.0, sel_idx, L_off[nf + nm:], hs[nf + nm:], lj, dj)
         t_mode["separate_calls"] += timed(separate)
         compare(diff["separate_calls"], ref, outputs(reorder=True))
+        if g == 0:
+            # launch-bound regime: the same items in waves of SMALL_WAVE_ROWS rows, where the
+            # per-launch cost of ~10 launches per layer per wave is no longer hidden
+            K.kvop_set_wave_rows(SMALL_WAVE_ROWS)
+            for name, flags in (("eager", 0), ("graph", K.KVOP_MIXED_GRAPH),
+                                ("graph_persistent", K.KVOP_MIXED_GRAPH | K.KVOP_MIXED_PERSISTENT)):
+                K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op, item_list, flags)   # warm-up
+                ms_small = timed(lambda: K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op, item_list,
+                                                           flags))
+                small["items_per_s"][name] = (nf + nm + nj) / (ms_small / 1e3)
+                compare(small["differences"].setdefault(name, {"filter_logits": 0.0, "join_logits": 0.0,
+                                                               "map_logits": 0.0, "map_tokens": 0, "decisions": 0}),
+                        ref, outputs())
+            K.kvop_set_wave_rows(WAVE_ROWS)
+            log(f"waves of {SMALL_WAVE_ROWS} rows (group 0): {small}")
         if g == 0:        # where the time goes: per-class profile of one eager call and of the separate calls
             K.kvop_profile_start()
             K.kvop_mixed_eval(pool, ops, 1.0, sel_idx, L_off, hs, item_op, item_list, 0)
@@ -462,7 +479,7 @@ def bench_mixed(args, K, synth, dev):
                                    "5462 filter, 5461 map (8 ids over 256 labels), 2048 join pairs; r=1; bf16",
                        "groups": G, "items": n_items},
             "modes_items_per_s": {k: n_items / (v / 1e3) for k, v in t_mode.items()},
-            "differences_from_graph_mode": diff, "wave_rows": WAVE_ROWS,
+            "differences_from_graph_mode": diff, "wave_rows": WAVE_ROWS, "small_waves": small,
             "profile_group0_ms": {"eager_mixed": prof_mixed, "separate_calls": prof_sep},
             "kv_build_s": t_build, "gemm_tiles": tiles}
     print(json.dumps(line), flush=True)
