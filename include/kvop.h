@@ -14,10 +14,18 @@
  *     a join is a filter over pairs of the cartesian product (Section 4.2)
  *                                                                -> kvop_op_eval
  *   - query-agnostic compression keeps a fraction of each document's rows
- *     (Section 2.3, Section 5); the kept rows are passed in as index lists.
+ *     (Section 2.3, Section 5); the kept rows are passed in as index lists,
+ *     scored and selected by expected attention  -> kvop_kv_build_scored, kvop_ea_select
  *   - the learned proxy is the cheap first stage of a two-stage cascade: it
  *     answers confident items and passes the rest on as unsure (cascade
  *     semantics, Section 4.1 Eqs. 1-3)                           -> kvop_proxy_*
+ *   - a cascade over profiles of increasing retention evaluates each item only
+ *     until a stage decides it (Section 4.1, Eqs. 1-3)           -> kvop_cascade_eval
+ *   - the optimizer chooses the stages and thresholds of such cascades from
+ *     profiled log-odds under credible bounds on recall and precision, and
+ *     orders the chosen operators (Sections 4.1-4.2; host code)  -> kvop_plan_*
+ *   - several operators share every launch of one pass (Section 5, batching)
+ *                                                                -> kvop_mixed_eval
  *
  * Conventions for every call:
  *   - "dev" pointers are device (HBM) pointers on the current HIP device,
