@@ -381,13 +381,18 @@ kvop_status kvop_plan_reorder(int32_t n_ops, const int32_t* impl, const double* 
   if (n_ops < 1 || n_ops > 20 || !impl || !cost || !sel_inter || !sel_intra || !order_out || !cost_out ||
       !(n_tuples >= 0.0))
     return fail(KVOP_EINVAL, "need 1..20 operators and non-null arrays");
-  int n_log = 0;
+  // logical operators renumbered densely (at most n_ops of them), so the table is
+  // 2^n_ops x (distinct logical operators) pending counts
+  int dense[64], n_log = 0;
+  std::fill(dense, dense + 64, -1);
+  std::vector<int> lid(n_ops);
   for (int i = 0; i < n_ops; i++) {
     if (impl[i] < 0 || impl[i] >= 64) return fail(KVOP_EINVAL, "logical operator index out of range");
     if (!(sel_inter[i] >= 0.0 && sel_inter[i] <= 1.0 && sel_intra[i] >= 0.0 && sel_intra[i] <= 1.0) ||
         !(cost[i] >= 0.0) || !std::isfinite(cost[i]))
       return fail(KVOP_EINVAL, "selectivities must be in [0, 1], costs finite and >= 0");
-    n_log = std::max(n_log, impl[i] + 1);
+    if (dense[impl[i]] < 0) dense[impl[i]] = n_log++;
+    lid[i] = dense[impl[i]];
   }
   const uint32_t full = (1u << n_ops) - 1u;
   const double inf = std::numeric_limits<double>::infinity();
@@ -403,12 +408,12 @@ kvop_status kvop_plan_reorder(int32_t n_ops, const int32_t* impl, const double* 
     for (int i = 0; i < n_ops; i++) {
       if (S >> i & 1u) continue;
       uint32_t T = S | (1u << i);
-      double c = best[S] + cost[i] * r[impl[i]];
+      double c = best[S] + cost[i] * r[lid[i]];
       if (c < best[T]) {
         best[T] = c;
         parent[T] = (int8_t)i;
         double* rt = &rem[(size_t)T * n_log];
-        for (int l = 0; l < n_log; l++) rt[l] = r[l] * (l == impl[i] ? sel_intra[i] : sel_inter[i]);
+        for (int l = 0; l < n_log; l++) rt[l] = r[l] * (l == lid[i] ? sel_intra[i] : sel_inter[i]);
       }
     }
   }
