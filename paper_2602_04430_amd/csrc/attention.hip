@@ -344,7 +344,9 @@ __device__ void attn_unit(const AttnArgs& a, int unit, AttnSmem<TC, D>& sm) {
     const float c = a.scale_log2;
     const float m_new = fmaxf(m_run, mx);
     const float mc = m_new == -INFINITY ? 0.f : m_new * c;
-    const float alpha = __builtin_amdgcn_exp2f(m_run * c - mc);   // 0 when m_run = -inf
+    // rescale of the running sums: exactly 1 when the maximum did not move (the contracted
+    // m_run * c - mc is then the rounding error of mc, not 0), 0 when m_run = -inf
+    const float alpha = m_new > m_run ? __builtin_amdgcn_exp2f(m_run * c - mc) : 1.f;
     float psum = 0.f;
 #pragma unroll
     for (int b = 0; b < NB; b++)

@@ -4,7 +4,10 @@ configuration the benchmark times (all 4096 documents in one op_eval per r), wit
 documents checked one by one against the FP64 oracle for every (dtype, r).  Prints the
 error table: max-abs logit error and decisions outside the margin band.  The BF16 build is
 the scored one (kvop_kv_build_scored: identical caches), and the expected-attention scores of
-sampled documents are checked against the oracle's emulation of the BF16 form.
+sampled documents are checked against the oracle's emulation of the BF16 form.  On that build
+two properties are checked over all 4096 documents, bit for bit: the cascade executor over
+the expected-attention ladder equals Eqs. 1-3 applied to its stages' own evaluations, and
+padded batching equals the unpadded evaluation.
 
 Bounds at this shape:
   FP32                 E = 1e-4   (as at the small shapes)
@@ -124,6 +127,7 @@ def test_scale_filter_sampled_parity(device, scale_setup, request, compute, kv):
     E = E_SCALE[(compute, kv)]
     pos = {int(d): i for i, d in enumerate(sel)}
     failures = []
+    outs = {}
     for r in wl.r_grid:
         idx, offs = lists[r]
         sidx = np.concatenate([idx[offs[d]:offs[d + 1]] for d in sel])
@@ -133,6 +137,7 @@ def test_scale_filter_sampled_parity(device, scale_setup, request, compute, kv):
         K.kvop_op_eval(pool, op, r, torch.from_numpy(sidx).to(device), soffs, handles, lg, dec)
         torch.cuda.synchronize()
         lg, dec = lg.cpu().numpy().astype(np.float64), dec.cpu().numpy()
+        outs[r] = (lg, dec)
         got = np.stack([lg[pos[i]] for i in SAMPLE])
         exp = np.stack([ref[(i, r)].logits for i in SAMPLE])
         err = float(np.max(np.abs(got - exp)))
@@ -162,6 +167,73 @@ def test_scale_filter_sampled_parity(device, scale_setup, request, compute, kv):
             say(line)
             if err > E_EA:
                 failures.append(line)
+        failures += _cascade_and_padding_at_scale(pool, op, handles, scores, sub, lists, outs, device)
     K.kvop_pool_destroy(pool)
     K.kvop_model_destroy(model)
     assert not failures, failures
+
+
+def _cascade_and_padding_at_scale(pool, op, handles, scores, sub, lists, outs, device):
+    """At the benchmark's size (all 4096 documents in one call), properties that need no
+    oracle: the cascade over the expected-attention profiles r = 0.1 -> 0.25 -> 0.5 and the
+    full r = 1 list equals Eqs. 1-3 applied to each stage's own full evaluation (stage,
+    decision and logits bit for bit, Eq. 4's counts), and padded batching reproduces the
+    unpadded r = 0.25 evaluation bit for bit."""
+    failures = []
+    n = len(sub.lengths)
+    stage_lists = {}
+    for r in (0.1, 0.25, 0.5):
+        total = sum(K.kvop_retained_count(r, int(L)) for L in sub.lengths)
+        idx_r = torch.empty(total, dtype=torch.int32, device=device)
+        stage_lists[r] = (idx_r, K.kvop_ea_select(pool, scores, sub.offsets, r, idx_r))
+    stage_lists[1.0] = (torch.from_numpy(lists[1.0][0]).to(device), lists[1.0][1])
+    rs = (0.1, 0.25, 0.5, 1.0)
+
+    def evaluate(r, theta, flags=0):
+        o = K.make_op(K.KVOP_FILTER, op._keep, synth.YES_ID, synth.NO_ID, theta, -theta, flags=flags)
+        lg = torch.empty(n, 2, dtype=torch.float32, device=device)
+        dec = torch.empty(n, dtype=torch.int8, device=device)
+        K.kvop_op_eval(pool, o, r, stage_lists[r][0], stage_lists[r][1], handles, lg, dec)
+        torch.cuda.synchronize()
+        return lg.cpu().numpy(), dec.cpu().numpy()
+
+    th = []
+    for r in rs[:-1]:
+        lg, _ = evaluate(r, 0.0)
+        th.append(float(np.float32(np.quantile(np.abs(lg[:, 0] - lg[:, 1]), 0.5))))
+    th.append(0.0)
+    table = [evaluate(r, t) for r, t in zip(rs, th)]
+    first = np.full(n, len(rs) - 1)
+    for t in range(n):
+        d = [i for i in range(len(rs)) if table[i][1][t] != -1]
+        if d:
+            first[t] = d[0]
+    o = K.make_op(K.KVOP_FILTER, op._keep, synth.YES_ID, synth.NO_ID)
+    lg = torch.empty(n, 2, dtype=torch.float32, device=device)
+    dec = torch.empty(n, dtype=torch.int8, device=device)
+    stg = torch.empty(n, dtype=torch.int8, device=device)
+    proc = K.kvop_cascade_eval(pool, o, [(r, t, -t, *stage_lists[r]) for r, t in zip(rs, th)], handles, lg, dec, stg)
+    torch.cuda.synchronize()
+    lg, dec, stg = lg.cpu().numpy(), dec.cpu().numpy(), stg.cpu().numpy()
+    ok = (np.array_equal(stg, first) and np.array_equal(dec, [table[s][1][t] for t, s in enumerate(first)])
+          and np.array_equal(lg, np.stack([table[s][0][t] for t, s in enumerate(first)]))
+          and list(proc) == [int(np.sum(first >= i)) for i in range(len(rs))])
+    line = f"cascade at scale: processed {list(proc)}, equals its per-stage evaluations: {ok}"
+    say(line)
+    if not ok:
+        failures.append(line)
+    idx, offs = lists[0.25]
+    o = K.make_op(K.KVOP_FILTER, op._keep, synth.YES_ID, synth.NO_ID, flags=K.KVOP_FLAG_PADDED)
+    lgp = torch.empty(n, 2, dtype=torch.float32, device=device)
+    decp = torch.empty(n, dtype=torch.int8, device=device)
+    K.kvop_op_eval(pool, o, 0.25, torch.from_numpy(idx).to(device), offs, handles, lgp, decp)
+    torch.cuda.synchronize()
+    lgp = lgp.cpu().numpy().astype(np.float64)
+    ok = np.array_equal(lgp, outs[0.25][0]) and np.array_equal(decp.cpu().numpy(), outs[0.25][1])
+    line = (f"padded batching at scale (r = 0.25): equals the unpadded evaluation: {ok} "
+            f"(max |difference| {float(np.max(np.abs(lgp - outs[0.25][0]))):.3g}, "
+            f"items differing {int(np.sum(np.any(lgp != outs[0.25][0], axis=1)))})")
+    say(line)
+    if not ok:
+        failures.append(line)
+    return failures
