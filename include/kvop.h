@@ -248,8 +248,9 @@ typedef struct kvop_stage {
  * unsure.  Outputs (device, one row per item): the logits and decision of the last stage
  * that evaluated the item (decision -1 if it is still unsure after the last stage) and that
  * stage's index in stage_out_dev (int8).  processed_host[n_stages] receives the number of
- * items each stage evaluated (Eq. 4's unsure counts).  The call synchronises `stream`
- * between stages (the unsure set is compacted on the host).  Errors: EINVAL (a map, no
+ * items each stage evaluated (Eq. 4's unsure counts).  Every stage's lists are validated
+ * before the first stage runs, so an argument error leaves the outputs untouched.  The call
+ * synchronises `stream` between stages (the unsure set is compacted on the host).  Errors: EINVAL (a map, no
  * stages or more than 127, null pointers, a NaN threshold), and those of kvop_op_eval_select. */
 kvop_status kvop_cascade_eval(kvop_pool* pool, const kvop_op* op, const kvop_stage* stages, int32_t n_stages,
                               const kvop_handle* handles_host, int32_t n_items, void* stream, float* logits_out_dev,

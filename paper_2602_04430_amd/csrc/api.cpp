@@ -834,7 +834,8 @@ kvop_status kvop_ea_select(kvop_pool* p, const float* scores, const int64_t* off
 // ------------------------------------------------------------------ op_eval
 static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
                                 const kvop_handle* hs, int32_t n_items, const int32_t* select, int32_t n_select,
-                                void* stream, float* logits, int8_t* decision, int32_t* tokens_out) {
+                                void* stream, float* logits, int8_t* decision, int32_t* tokens_out,
+                                bool validate_only = false) {
   if (!p || !op || n_items < 0 || n_select < 0) return fail(KVOP_EINVAL, "bad arguments");
   if (n_items == 0 || (select && n_select == 0)) return KVOP_OK;
   kvop_model* m = p->m;
@@ -907,6 +908,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     if (m->hflag[0] != 0)
       return fail(KVOP_EINVAL, std::to_string(m->hflag[0]) + " index list(s) unsorted or out of range");
   }
+  if (validate_only) return KVOP_OK;
 
   const int d = c.d_model, H = c.n_heads, Hkv = c.n_kv_heads, D = c.head_dim, G = H / Hkv, F = c.d_ffn;
   const int qc = m->qkv_cols();
@@ -1202,6 +1204,16 @@ kvop_status kvop_cascade_eval(kvop_pool* p, const kvop_op* op, const kvop_stage*
   }
   if (n_items == 0) return KVOP_OK;
   hipStream_t st = (hipStream_t)stream;
+  // every stage's arguments and lists are checked before any stage runs, so that an
+  // argument error leaves the outputs untouched
+  for (int i = 0; i < n_stages; i++) {
+    kvop_op o = *op;
+    o.theta_pos = stages[i].theta_pos;
+    o.theta_neg = stages[i].theta_neg;
+    kvop_status s = op_eval_impl(p, &o, stages[i].r, stages[i].idx_dev, stages[i].idx_offsets_host, hs, n_items,
+                                 nullptr, 0, stream, logits, decision, nullptr, true);
+    if (s != KVOP_OK) return s;
+  }
   std::vector<int32_t> sel(n_items);
   for (int t = 0; t < n_items; t++) sel[t] = t;               // every item starts unsure
   std::vector<int8_t> dec(n_items, -1), stage_of(n_items, -1);

@@ -198,6 +198,21 @@ def test_degenerate_cascades(device):
         _cascade(eng, K.KVOP_FILTER, h, suffix, [])
     with pytest.raises(K.KvopError):
         _cascade(eng, K.KVOP_FILTER, h, suffix, [(0.5, float("nan"), 0.0, *lists[0.5])])
+    # a bad list in a later stage (unsorted rows) is found before any stage runs: outputs untouched
+    bad_idx = lists[1.0][0].copy()
+    i3 = int(np.flatnonzero(np.diff(lists[1.0][1]) >= 2)[0])
+    o0 = int(lists[1.0][1][i3])
+    bad_idx[o0], bad_idx[o0 + 1] = bad_idx[o0 + 1], bad_idx[o0]
+    op = K.make_op(K.KVOP_FILTER, suffix, synth.YES_ID, synth.NO_ID)
+    lg = torch.full((40, 2), 123.0, device="cuda")
+    dec = torch.full((40,), 7, dtype=torch.int8, device="cuda")
+    stg = torch.full((40,), 9, dtype=torch.int8, device="cuda")
+    with pytest.raises(K.KvopError):
+        K.kvop_cascade_eval(eng.pool, op, [(0.25, 0.5, -0.5, torch.from_numpy(lists[0.25][0]).cuda(), lists[0.25][1]),
+                                           (1.0, 0.0, 0.0, torch.from_numpy(bad_idx).cuda(), lists[1.0][1])],
+                            h, lg, dec, stg)
+    torch.cuda.synchronize()
+    assert bool((lg == 123.0).all()) and bool((dec == 7).all()) and bool((stg == 9).all())
     op = K.make_op(K.KVOP_MAP, suffix, label_lo=0, label_n=4, n_gen=1)
     buf = torch.zeros(40, 2, device="cuda")
     with pytest.raises(K.KvopError):
