@@ -178,6 +178,16 @@ def test_error_paths(device):
     K.kvop_kv_release(eng.pool, handles[:1])
     assert status(lambda: eng.filter(handles, idx, offs, suffix)) == K.KVOP_EBADHANDLE
     assert status(lambda: K.kvop_kv_release(eng.pool, handles[:1])) == K.KVOP_EBADHANDLE
+    # empty inputs: no documents, no items (outputs untouched); an empty document is refused
+    empty = synth.Docs(np.zeros(0, np.int64), np.zeros(0, np.int32), np.zeros(1, np.int64))
+    assert len(eng.build(empty)) == 0
+    lg0 = torch.full((1, 2), 5.0, device="cuda")
+    K.kvop_op_eval(eng.pool, K.make_op(K.KVOP_FILTER, suffix), 1.0, torch.zeros(1, dtype=torch.int32, device="cuda"),
+                   [0], np.zeros(0, np.uint64), lg0)
+    torch.cuda.synchronize()
+    assert bool((lg0 == 5.0).all())
+    hole = synth.Docs(np.array([3, 0, 2], np.int64), np.zeros(5, np.int32), np.array([0, 3, 3, 5], np.int64))
+    assert status(lambda: eng.build(hole)) == K.KVOP_EINVAL
     big = synth.make_docs_uniform(200, 400, 400, shape.vocab, seed=7)                          # too big for 4 MiB
     u0 = K.kvop_pool_stats(eng.pool)
     assert status(lambda: eng.build(big)) == K.KVOP_ENOMEM
