@@ -42,6 +42,8 @@ hipError_t embed_suffix(int dt, const void* E, const int32_t* suffix, int S, int
 }
 
 // ---------------------------------------------------------------- RMSNorm
+// One wavefront per row.  Rows of up to 8 x 256 values stay in registers between the sum of
+// squares and the scaling (one read of x); the output is written 4 values per lane per store.
 template <typename TO>
 __global__ __launch_bounds__(256) void rmsnorm_kernel(const float* __restrict__ x, int64_t ldx,
                                                       const float* __restrict__ g, int n_rows, int d, float eps,
@@ -50,26 +52,49 @@ __global__ __launch_bounds__(256) void rmsnorm_kernel(const float* __restrict__ 
   int lane = threadIdx.x & 63;
   if (row >= n_rows) return;
   const float* xr = x + (int64_t)row * ldx;
+  TO* yr = y + (int64_t)row * ldy;
+  constexpr int KEEP = 8;                     // 16-byte pieces per lane kept in registers
+  f32x4 keep[KEEP];
   float ss = 0.f;
-  for (int c = lane * 4; c < d; c += 256) {
+#pragma unroll
+  for (int it = 0; it < KEEP; it++) {
+    const int c = lane * 4 + 256 * it;
+    if (c < d) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(xr + c);
+      keep[it] = v;
+      ss += v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+    }
+  }
+  for (int c = lane * 4 + 256 * KEEP; c < d; c += 256) {
     f32x4 v = *reinterpret_cast<const f32x4*>(xr + c);
     ss += v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
   }
   ss = wave_sum(ss);
   float inv = 1.0f / sqrtf(ss / (float)d + eps);
-  TO* yr = y + (int64_t)row * ldy;
-  for (int c = lane * 4; c < d; c += 256) {
-    f32x4 v = *reinterpret_cast<const f32x4*>(xr + c);
-    f32x4 gg = *reinterpret_cast<const f32x4*>(g + c);
+  auto put = [&](int c, const f32x4& v) {
+    const f32x4 gg = *reinterpret_cast<const f32x4*>(g + c);
+    if constexpr (sizeof(TO) == 2) {
+      u32x2 pk;
+      pk[0] = pack_bf16x2(v[0] * inv * gg[0], v[1] * inv * gg[1]);
+      pk[1] = pack_bf16x2(v[2] * inv * gg[2], v[3] * inv * gg[3]);
+      *reinterpret_cast<u32x2*>(yr + c) = pk;
+    } else {
+      *reinterpret_cast<f32x4*>(yr + c) =
+          f32x4{v[0] * inv * gg[0], v[1] * inv * gg[1], v[2] * inv * gg[2], v[3] * inv * gg[3]};
+    }
+  };
 #pragma unroll
-    for (int e = 0; e < 4; e++) yr[c + e] = from_f32<TO>(v[e] * inv * gg[e]);
+  for (int it = 0; it < KEEP; it++) {
+    const int c = lane * 4 + 256 * it;
+    if (c < d) put(c, keep[it]);
   }
+  for (int c = lane * 4 + 256 * KEEP; c < d; c += 256) put(c, *reinterpret_cast<const f32x4*>(xr + c));
 }
 
 hipError_t rmsnorm_rows(int dt, const float* x, int64_t ldx, const float* g, int n_rows, int d, float eps, void* y,
                         int64_t ldy, hipStream_t st) {
   if (n_rows <= 0) return hipSuccess;
-  if (d % 4 || ldx % 4) return hipErrorInvalidValue;
+  if (d % 4 || ldx % 4 || ldy % 4) return hipErrorInvalidValue;   // 16- and 8-byte row accesses
   dim3 grid((n_rows + 3) / 4);
   if (dt == DT_F32)
     hipLaunchKernelGGL(rmsnorm_kernel<float>, grid, dim3(256), 0, st, x, ldx, g, n_rows, d, eps, (float*)y, ldy);
