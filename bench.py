@@ -321,6 +321,7 @@ def bench_mixed(args, K, synth, dev):
     caches exceed HBM, so the items are processed in groups whose documents fit: each
     group's caches are built (untimed), then its items are evaluated (timed)."""
     import torch
+    from paper_2602_04430_amd import batching
     shape = synth.SCALE
     wl = synth.mixed_batch(0)
     docs = wl.docs
@@ -340,17 +341,7 @@ def bench_mixed(args, K, synth, dev):
     K.kvop_pool_destroy(probe)
     cap = torch.cuda.mem_get_info()[0] - (48 << 30)
     pool = K.kvop_pool_create(mb, K.KVOP_KV_BF16, cap)
-    G = 1
-    while True:
-        ok = True
-        for g in range(G):
-            need = set(np.array_split(fdocs, G)[g]) | set(np.array_split(mdocs, G)[g]) | \
-                set(np.array_split(pairs, G)[g].ravel().tolist())
-            if dbytes[sorted(need)].sum() > cap - (2 << 30):
-                ok = False
-        if ok:
-            break
-        G += 1
+    G = batching.plan_groups(dbytes, fdocs, mdocs, pairs, cap - (2 << 30))
     log(f"mixed workload: {len(fdocs)} filter, {len(mdocs)} map, {len(pairs)} join items in {G} groups")
     # tune the projections at the row counts the waves run: full waves, and the per-operator
     # last-layer rows and decode rows
@@ -371,8 +362,8 @@ def bench_mixed(args, K, synth, dev):
     # captured graph is replayed (the first wave and a partial last wave run directly)
     K.kvop_set_wave_rows(WAVE_ROWS)
     for g in range(G):
-        fg, mg, pg = np.array_split(fdocs, G)[g], np.array_split(mdocs, G)[g], np.array_split(pairs, G)[g]
-        need = sorted(set(fg) | set(mg) | set(pg.ravel().tolist()))
+        fg, mg, pg = batching.group_parts(fdocs, mdocs, pairs, G, g)
+        need = batching.group_docs(fg, mg, pg)
         sub = docs.subset(need)
         pos = {dd: i for i, dd in enumerate(need)}
         torch.cuda.synchronize()
@@ -391,13 +382,10 @@ def bench_mixed(args, K, synth, dev):
         sel_idx = torch.cat([idx[int(foffs[i]):int(foffs[i + 1])] for i in all_lists])
         hs = hsub[all_lists]
         nf, nm, nj = len(lists_f), len(lists_m), len(pg)
-        item_op = np.concatenate([np.zeros(nf), np.ones(nm), 2 * np.ones(nj)]).astype(np.int32)
-        item_list = np.concatenate([np.arange(nf), nf + np.arange(nm), nf + nm + 2 * np.arange(nj)]).astype(np.int64)
-        perm = np.random.default_rng(g).permutation(len(item_op))      # operators interleaved
-        item_op, item_list = item_op[perm], item_list[perm]
+        item_op, item_list = batching.interleave(nf, nm, nj, seed=g)      # operators interleaved
         # a mixed call writes operator k's outputs in the order its items appear in the
         # interleaved list; the separate calls write them in list order
-        order = [item_list[item_op == 0], item_list[item_op == 1] - nf, (item_list[item_op == 2] - nf - nm) // 2]
+        order = batching.output_order(item_op, item_list, nf, nm)
         n_items += nf + nm + nj
         lf = torch.empty(nf, 2, device=dev)
         df = torch.empty(nf, dtype=torch.int8, device=dev)

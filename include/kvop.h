@@ -121,9 +121,11 @@ kvop_status kvop_pool_stats(const kvop_pool* pool, uint64_t* used_bytes, uint64_
  *   pooled_dev   : optional FP32 [n_docs, d_model] output (NULL to skip): the mean
  *                  over the document's rows of the final-normed hidden state
  *                  (the learned proxy's input feature)
- * Errors: EINVAL (n_docs < 0, empty document, decreasing offsets); ENOMEM when the
- * pool cannot hold all documents (then no handle is created); token ids are not
- * range-checked on the host: ids outside [0, vocab) are clamped on the device. */
+ * Errors: EINVAL (n_docs < 0, empty document, decreasing offsets, a token id outside
+ * [0, vocab)); ENOMEM when the pool cannot hold all documents.  On any error no handle
+ * is created and nothing is written.  Token ids are checked on the device before any
+ * compute is enqueued, which synchronises `stream` once; the caches are then built
+ * asynchronously on `stream`. */
 kvop_status kvop_kv_build(kvop_pool* pool, const int32_t* tokens_dev, const int64_t* offsets_host,
                           int32_t n_docs, void* stream, kvop_handle* handles_out, float* pooled_dev);
 

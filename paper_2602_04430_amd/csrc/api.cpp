@@ -132,16 +132,43 @@ struct kvop_model {
   int* hflag = nullptr;
   int n_cu = 0;
   hipStream_t cap_stream = nullptr;  // graph capture (the legacy null stream cannot be captured)
+  // completion of the last call that used the workspaces, and the stream it ran on
+  hipEvent_t done_ev = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool done_recorded = false;
 
   int qkv_cols() const { return (cfg.n_heads + 2 * cfg.n_kv_heads) * cfg.head_dim; }
   int esz() const { return dt == DT_F32 ? 4 : 2; }
   ~kvop_model() {
+    if (done_ev) { (void)hipEventSynchronize(done_ev); (void)hipEventDestroy(done_ev); }
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     if (dflag) (void)hipFree(dflag);
     if (hflag) (void)hipHostFree(hflag);
   }
 };
+
+namespace {
+// Calls on one model share its workspaces (activations, metadata, flags) and its pools'
+// freed regions.  A call enqueued on another stream than the previous call first waits for
+// that call's completion event, so nothing it overwrites is still being read.  Constructed
+// before a call's first enqueue; the destructor records the call's completion.
+struct CallOrder {
+  kvop_model* m;
+  hipStream_t st;
+  CallOrder(kvop_model* m_, hipStream_t st_) : m(m_), st(st_) {
+    if (m->done_recorded && m->last_stream != st) (void)hipStreamWaitEvent(st, m->done_ev, 0);
+  }
+  ~CallOrder() {
+    if (!m->done_ev && hipEventCreateWithFlags(&m->done_ev, hipEventDisableTiming) != hipSuccess) {
+      m->done_ev = nullptr;
+      return;
+    }
+    m->done_recorded = hipEventRecord(m->done_ev, st) == hipSuccess;
+    m->last_stream = st;
+  }
+};
+}  // namespace
 
 struct DocSlot {
   uint64_t off = 0, bytes = 0;
@@ -585,6 +612,7 @@ static kvop_status kv_build_impl(kvop_pool* p, const int32_t* tokens, const int6
   kvop_model* m = p->m;
   const kvop_model_cfg& c = m->cfg;
   hipStream_t st = (hipStream_t)stream;
+  CallOrder order(m, st);
   for (int i = 0; i < n; i++) {
     int64_t L = offsets[i + 1] - offsets[i];
     if (L < 1) return fail(KVOP_EINVAL, "document " + std::to_string(i) + " is empty or offsets decrease");
@@ -592,6 +620,13 @@ static kvop_status kv_build_impl(kvop_pool* p, const int32_t* tokens, const int6
     if (scores && L + n_future > kRopeMaxPos)
       return fail(KVOP_EINVAL, "document " + std::to_string(i) + ": L + n_future exceeds the rotary table");
   }
+  // token ids must lie in [0, V): checked on the device, before anything is allocated or
+  // any compute is enqueued (one synchronisation of the stream)
+  HIPTRY(hipMemsetAsync(m->dflag, 0, 4, st));
+  HIPTRY(validate_tokens(tokens + offsets[0], offsets[n] - offsets[0], c.vocab, m->dflag, st));
+  HIPTRY(hipMemcpyAsync(m->hflag, m->dflag, 4, hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  if (m->hflag[0] != 0) return fail(KVOP_EINVAL, "token id outside [0, vocab)");
   // expected-attention workspace (model-owned, grown on demand): per chunk row, H
   // log-weights and Hkv accumulators
   float* ea_ws = nullptr;
@@ -812,6 +847,7 @@ kvop_status kvop_ea_select(kvop_pool* p, const float* scores, const int64_t* off
   }
   doc_off[n] = offsets[n] - offsets[0];
   kvop_model* m = p->m;
+  CallOrder order(m, st);
   Mirror mir;
   size_t o_doc = mir.add((n + 1) * 8), o_out = mir.add((n + 1) * 8), o_k = mir.add(n * 4);
   if (m->stage.reserve(mir.size) != hipSuccess || m->meta.reserve(mir.size, st) != hipSuccess)
@@ -893,6 +929,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     int64_t top = join ? (int64_t)docs[2 * i]->L + docs[2 * i + 1]->L : docs[i]->L;
     if (top + S + n_gen >= kRopeMaxPos) return fail(KVOP_EINVAL, "positions exceed the rotary table");
   }
+  CallOrder order(m, st);
   // device-side validation of the lists (sorted, in range), before any compute
   {
     Mirror mir;
@@ -1308,6 +1345,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     if (top + o.suffix_len + (o.kind == KVOP_MAP ? o.n_gen : 1) >= kRopeMaxPos)
       return fail(KVOP_EINVAL, "positions exceed the rotary table");
   }
+  CallOrder order(m, st);
   {
     Mirror mir;
     size_t o_chk = mir.add(checks.size() * sizeof(ListCheck));

@@ -15,7 +15,7 @@ __global__ void embed_kernel(const T* __restrict__ E, const int32_t* __restrict_
   int row = blockIdx.x;
   if (row >= n_rows) return;
   int t = S > 0 ? tok[row % S] : tok[row];
-  t = min(max(t, 0), vocab - 1);
+  t = min(max(t, 0), vocab - 1);  // ids are validated by the callers; the clamp only guards the gather
   const T* e = E + (int64_t)t * d;
   float* o = x + (int64_t)row * d;
   for (int c = threadIdx.x; c < d; c += blockDim.x) o[c] = to_f32(e[c]);
@@ -497,6 +497,25 @@ __global__ __launch_bounds__(256) void validate_kernel(const int32_t* __restrict
 hipError_t validate_lists(const int32_t* idx, const ListCheck* lists, int n_lists, int* bad, hipStream_t st) {
   if (n_lists <= 0) return hipSuccess;
   hipLaunchKernelGGL(validate_kernel, dim3((n_lists + 3) / 4), dim3(256), 0, st, idx, lists, n_lists, bad);
+  return hipGetLastError();
+}
+
+// Token ids outside [0, vocab): one count per wavefront that saw any.
+__global__ __launch_bounds__(256) void validate_tokens_kernel(const int32_t* __restrict__ tok, int64_t n, int vocab,
+                                                              int* __restrict__ bad) {
+  int ok = 1;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    int t = tok[i];
+    if (t < 0 || t >= vocab) ok = 0;
+  }
+  ok = __all(ok);
+  if ((threadIdx.x & 63) == 0 && !ok) atomicAdd(bad, 1);
+}
+
+hipError_t validate_tokens(const int32_t* tok, int64_t n, int vocab, int* bad, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(validate_tokens_kernel, dim3((unsigned)blocks), dim3(256), 0, st, tok, n, vocab, bad);
   return hipGetLastError();
 }
 

@@ -157,6 +157,8 @@ struct ListCheck {
   int32_t n, L;
 };
 hipError_t validate_lists(const int32_t* idx, const ListCheck* lists, int n_lists, int* bad, hipStream_t st);
+// counts, into *bad, the wavefronts that saw a token id outside [0, vocab)
+hipError_t validate_tokens(const int32_t* tok, int64_t n, int vocab, int* bad, hipStream_t st);
 // weight conversion: dst (dt) = src (f32); for interleave16 != 0 the rows of two [F, d]
 // matrices (src, src2) are interleaved in blocks of 16
 hipError_t convert_weights(int dt, const float* src, const float* src2, int64_t rows, int64_t cols, void* dst,

@@ -75,3 +75,31 @@ def decisions_agree_outside_band(lo_ref, dec_gpu, E, theta=0.0):
     ref = np.where(lo_ref > theta, 1, np.where(lo_ref < theta, 0, -1))
     out = np.abs(lo_ref - theta) >= 2 * E
     return int(np.sum((ref != dec_gpu) & out)), float(1 - out.mean())
+
+
+def check_map(tokens_gpu, logits_gpu, refs, E):
+    """Map items against the oracle's greedy decodes (refs: oracle MapResult per item).
+
+    An id is decision-pinned while every oracle step so far, this one included, has a top-1 to
+    top-2 margin of at least 2 E over the label slice: there a result within E of the oracle's
+    logits cannot pick another id, so the GPU's ids must equal the oracle's up to the item's
+    first in-band step.  The slice logits must be within E at every step whose earlier ids
+    agree (after a divergence inside the band the two decode different texts).
+    Returns (ids checked, items with all ids checked, max-abs logit error, failures)."""
+    checked, whole, err, fails = 0, 0, 0.0, []
+    for i, res in enumerate(refs):
+        srt = np.sort(res.step_logits, axis=1)
+        pinned = np.cumprod(srt[:, -1] - srt[:, -2] >= 2 * E).astype(bool)
+        for t in range(len(res.tokens)):
+            if not np.array_equal(tokens_gpu[i, :t], res.tokens[:t]):
+                break
+            e = float(np.max(np.abs(logits_gpu[i, t] - res.step_logits[t])))
+            err = max(err, e)
+            if e > E:
+                fails.append(("logits", i, t, e))
+        n = int(pinned.sum())
+        checked += n
+        whole += int(n == len(res.tokens))
+        if not np.array_equal(tokens_gpu[i, :n], res.tokens[:n]):
+            fails.append(("ids", i, tokens_gpu[i].tolist(), res.tokens.tolist(), n))
+    return checked, whole, err, fails
