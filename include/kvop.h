@@ -321,6 +321,19 @@ kvop_status kvop_proxy_grads(kvop_proxy* proxy, const float* feats_dev, const in
 /* Inference over n rows: class (0/1), confidence max(p), answered = confidence > tau. */
 kvop_status kvop_proxy_infer(kvop_proxy* proxy, const float* feats_dev, int64_t n, float tau, void* stream,
                              int8_t* cls_out_dev, float* conf_out_dev, int8_t* answered_out_dev);
+/* kvop_proxy_infer that allocates nothing, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid it).  Same kernels
+ * and results as kvop_proxy_infer.  Its scratch (the standardised BF16 features and the
+ * FP32 hidden pre-activations of the call's rows) is a fixed device array of
+ * KVOP_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; its address is looked
+ * up on the first call on each device.  n is limited to
+ *   n * (2 d_in + 4 d_hidden) + 256 <= KVOP_NOALLOC_SCRATCH_BYTES
+ * (6553 rows for d_in 2048, d_hidden 256); larger n: EINVAL, nothing enqueued.  Every call
+ * on one GPU uses the same array: calls that overlap on one GPU (several streams or host
+ * threads) race and must be serialised by the caller. */
+#define KVOP_NOALLOC_SCRATCH_BYTES (32u << 20)
+kvop_status kvop_proxy_infer_noalloc(kvop_proxy* proxy, const float* feats_dev, int64_t n, float tau, void* stream,
+                                     int8_t* cls_out_dev, float* conf_out_dev, int8_t* answered_out_dev);
 /* Copy the FP32 master parameters (packed as above) into params_out_dev. */
 kvop_status kvop_proxy_params(kvop_proxy* proxy, float* params_out_dev, void* stream);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -83,6 +84,33 @@ kvop_status proxy_backward(kvop_proxy* p, const float* feats, const int32_t* lab
   }
   HIPTRY(proxy_reduce(w->a, w->dz, w->dh1, w->loss_row, B, H, p->grads + p->o_b1(), p->grads + p->o_w2(),
                       p->grads + p->o_b2(), w->loss, st));
+  return KVOP_OK;
+}
+
+// Scratch of the allocation-free inference: for one call's rows the standardised BF16
+// features [n, d_in], then (256-byte aligned) the FP32 hidden pre-activations [n, d_hidden].
+// One copy per GPU, held until the process ends.  Host code never uses this name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[KVOP_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first call per device).
+kvop_status scratch_address(void** out) {
+  int dev = -1;
+  HIPTRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(KVOP_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(KVOP_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return KVOP_OK;
 }
 
@@ -185,6 +213,31 @@ kvop_status kvop_proxy_infer(kvop_proxy* p, const float* feats, int64_t n, float
     HIPTRY(proxy_head_infer(w.h1, B, p->H, p->params + p->o_b1(), p->params + p->o_w2(), p->params + p->o_b2(), tau,
                             cls + r0, conf + r0, answered + r0, st));
   }
+  return KVOP_OK;
+}
+
+kvop_status kvop_proxy_infer_noalloc(kvop_proxy* p, const float* feats, int64_t n, float tau, void* stream,
+                                     int8_t* cls, float* conf, int8_t* answered) {
+  if (!p || (n > 0 && (!feats || !cls || !conf || !answered)) || n < 0) return fail(KVOP_EINVAL, "bad arguments");
+  const int64_t d = p->d, H = p->H;
+  const int64_t max_rows = ((int64_t)KVOP_NOALLOC_SCRATCH_BYTES - 256) / (2 * d + 4 * H);
+  if (n > max_rows)
+    return fail(KVOP_EINVAL, "kvop_proxy_infer_noalloc takes at most " + std::to_string(max_rows) + " rows for d_in " +
+                                 std::to_string(d) + ", d_hidden " + std::to_string(H) + " (" + std::to_string(n) +
+                                 " given): split the call");
+  if (n == 0) return KVOP_OK;
+  void* base = nullptr;
+  kvop_status s = scratch_address(&base);
+  if (s != KVOP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  uint16_t* x = (uint16_t*)base;
+  float* h1 = (float*)((char*)base + align_up(n * d * 2, 256));
+  const int B = (int)n;
+  HIPTRY(proxy_gather(feats, p->d, nullptr, B, p->mean, p->istd, x, nullptr, st));
+  GemmShape g{B, p->H, p->d, p->d, p->d, p->H};
+  HIPTRY(gemm(DT_BF16, DT_F32, EPI_STORE, gemm_pick_tile(DT_BF16, EPI_STORE, g), x, p->w1b, h1, g, st));
+  HIPTRY(proxy_head_infer(h1, B, p->H, p->params + p->o_b1(), p->params + p->o_w2(), p->params + p->o_b2(), tau, cls,
+                          conf, answered, st));
   return KVOP_OK;
 }
 

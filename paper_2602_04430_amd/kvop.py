@@ -88,6 +88,7 @@ _SIGS = {
     "kvop_proxy_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
     "kvop_proxy_grads": (C.c_int, [_P, _P, _P, _P, C.c_int32, _P, _P, _P]),
     "kvop_proxy_infer": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
+    "kvop_proxy_infer_noalloc": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
     "kvop_proxy_params": (C.c_int, [_P, _P, _P]),
     "kvop_set_wave_rows": (C.c_int, [C.c_int64]),
     "kvop_set_attention_kernel": (C.c_int, [C.c_int32]),
@@ -364,6 +365,12 @@ def kvop_proxy_grads(proxy, feats_dev, labels_dev, rows_dev, batch: int, grads_d
 def kvop_proxy_infer(proxy, feats_dev, tau: float, cls_dev, conf_dev, answered_dev, stream=None) -> None:
     _check(lib().kvop_proxy_infer(proxy, _dptr(feats_dev), int(feats_dev.shape[0]), tau, _stream(stream),
                                   _dptr(cls_dev), _dptr(conf_dev), _dptr(answered_dev)))
+
+
+def kvop_proxy_infer_noalloc(proxy, feats_dev, tau: float, cls_dev, conf_dev, answered_dev, stream=None) -> None:
+    """kvop_proxy_infer without device allocation (fixed per-GPU scratch; bounded row count)."""
+    _check(lib().kvop_proxy_infer_noalloc(proxy, _dptr(feats_dev), int(feats_dev.shape[0]), tau, _stream(stream),
+                                          _dptr(cls_dev), _dptr(conf_dev), _dptr(answered_dev)))
 
 
 def kvop_proxy_params(proxy, out_dev, stream=None) -> None:
