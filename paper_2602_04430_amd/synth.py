@@ -24,7 +24,7 @@ WEIGHT_STD = 0.02
 
 # Stream ids for SeedSequence spawn keys: each kind of input draws from its
 # own independent stream, so adding one input never shifts another.
-_S_WEIGHTS, _S_LENGTHS, _S_TOKENS, _S_SUFFIX, _S_RETAIN, _S_PROXY, _S_PAIRS = range(7)
+_S_WEIGHTS, _S_LENGTHS, _S_TOKENS, _S_SUFFIX, _S_RETAIN, _S_PROXY, _S_PAIRS, _S_TOPICS = range(8)
 
 
 @dataclass(frozen=True)
@@ -156,6 +156,25 @@ def doc_tokens(lengths: Sequence[int], vocab: int, seed: int, stream: int = 0) -
     np.cumsum(lengths, out=offsets[1:])
     toks = _rng(seed, _S_TOKENS, stream).integers(0, vocab, size=int(offsets[-1])).astype(np.int32)
     return toks, offsets
+
+
+def topic_docs(n: int, n_topics: int, topic_size: int, lo: int, hi: int, vocab: int, seed: int,
+               stream: int = 0) -> Tuple["Docs", np.ndarray]:
+    """Documents about topics: n_topics token sets of topic_size ids each (drawn once per
+    seed, shared by every stream); each document picks a topic uniformly and draws its
+    tokens uniformly from that topic's set, with a length uniform in [lo, hi].  Returns the
+    documents and each document's topic.  Collections of documents on a few subjects are
+    what a semantic filter sorts; the topics give the documents the structure a cheap
+    model of the pooled document state can learn."""
+    trng = _rng(seed, _S_TOPICS, 0)
+    topics = np.stack([trng.choice(vocab, topic_size, replace=False) for _ in range(n_topics)])
+    rng = _rng(seed, _S_TOPICS, 1 + stream)
+    which = rng.integers(0, n_topics, size=n)
+    L = rng.integers(lo, hi + 1, size=n).astype(np.int64)
+    offsets = np.zeros(n + 1, np.int64)
+    np.cumsum(L, out=offsets[1:])
+    toks = np.concatenate([topics[t][rng.integers(0, topic_size, size=int(l))] for t, l in zip(which, L)])
+    return Docs(L, toks.astype(np.int32), offsets), which
 
 
 def suffix_tokens(length: int, vocab: int, seed: int, which: int = 0) -> np.ndarray:

@@ -13,28 +13,29 @@ from tests.gpu_common import Engine, say
 pytestmark = pytest.mark.gpu
 
 D_IN, H = 256, 128
+SIZES = [(256, 128), (2048, 256)]      # a small shape, and the proxy's full 2048 -> 256 -> 2
 
 
 def _pack(p):
     return np.concatenate([p["w1"].ravel(), p["b1"], p["w2"].ravel(), p["b2"]]).astype(np.float32)
 
 
-def _unpack(v, d=D_IN, h=H):
+def _unpack(v, d, h):
     v = np.asarray(v, np.float64)
     o = h * d
     return {"w1": v[:o].reshape(h, d), "b1": v[o:o + h], "w2": v[o + h:o + 3 * h].reshape(2, h), "b2": v[o + 3 * h:]}
 
 
-def _setup(seed=0, n=64):
+def _setup(seed=0, n=64, d_in=D_IN, h=H):
     rng = np.random.default_rng(seed)
-    feats = (rng.standard_normal((n, D_IN)) * 0.7 + rng.standard_normal(D_IN) * 0.3).astype(np.float32)
+    feats = (rng.standard_normal((n, d_in)) * 0.7 + rng.standard_normal(d_in) * 0.3).astype(np.float32)
     labels = rng.integers(0, 2, n).astype(np.int32)
-    p0 = synth.proxy_init(D_IN, H, 2, seed)
-    p0["b1"] = (rng.standard_normal(H) * 0.05).astype(np.float32)
-    p0["w2"] = (rng.standard_normal((2, H)) * 0.2).astype(np.float32)
+    p0 = synth.proxy_init(d_in, h, 2, seed)
+    p0["b1"] = (rng.standard_normal(h) * 0.05).astype(np.float32)
+    p0["w2"] = (rng.standard_normal((2, h)) * 0.2).astype(np.float32)
     mean = feats.mean(axis=0).astype(np.float32)
     istd = (1.0 / np.maximum(feats.std(axis=0), 1e-6)).astype(np.float32)
-    px = K.kvop_proxy_create(D_IN, H, torch.from_numpy(_pack(p0)).cuda())
+    px = K.kvop_proxy_create(d_in, h, torch.from_numpy(_pack(p0)).cuda())
     K.kvop_proxy_set_standardizer(px, torch.from_numpy(mean).cuda(), torch.from_numpy(istd).cuda())
     return feats, labels, p0, mean, istd, px
 
@@ -43,14 +44,15 @@ def _std_bf16(feats, mean, istd):
     return codecs.bf16_round(((feats - mean) * istd).astype(np.float32)).astype(np.float64)
 
 
-def test_proxy_gradients_match_oracle(device):
-    feats, labels, p0, mean, istd, px = _setup(1, 64)
-    g = torch.empty(H * D_IN + 3 * H + 2, device=device)
+@pytest.mark.parametrize("d_in,h", SIZES)
+def test_proxy_gradients_match_oracle(device, d_in, h):
+    feats, labels, p0, mean, istd, px = _setup(1, 64, d_in, h)
+    g = torch.empty(h * d_in + 3 * h + 2, device=device)
     loss = torch.empty(1, device=device)
     rows = torch.arange(64, dtype=torch.int32, device=device).flip(0)      # a permuted minibatch
     K.kvop_proxy_grads(px, torch.from_numpy(feats).cuda(), torch.from_numpy(labels).cuda(), rows, 64, g, loss)
     torch.cuda.synchronize()
-    got = _unpack(g.cpu().numpy())
+    got = _unpack(g.cpu().numpy(), d_in, h)
     order = np.arange(64)[::-1]
     # reference on the operands the BF16 path actually multiplies (rounded x and W1)
     pr = {k: np.asarray(v, np.float64) for k, v in p0.items()}
@@ -60,7 +62,7 @@ def test_proxy_gradients_match_oracle(device):
     assert abs(float(loss.item()) - l_ref) < 1e-5
     for k, tol in (("w1", 1e-2), ("b1", 1e-4), ("w2", 1e-4), ("b2", 1e-5)):
         err = np.max(np.abs(got[k] - g_ref[k])) / max(1e-12, np.max(np.abs(g_ref[k])))
-        say("grad", k, err)
+        say("grad", d_in, h, k, err)
         assert err <= tol, (k, err)
     # against the plain FP64 oracle (unrounded operands) the BF16 error stays at the BF16 level
     l64, g64 = op.loss_and_grads({k: np.asarray(v, np.float64) for k, v in p0.items()},
@@ -86,8 +88,9 @@ def test_proxy_adam_step_matches_closed_form(device):
     K.kvop_proxy_destroy(px)
 
 
-def test_proxy_inference_matches_oracle(device):
-    feats, labels, p0, mean, istd, px = _setup(3, 300)
+@pytest.mark.parametrize("d_in,h", SIZES)
+def test_proxy_inference_matches_oracle(device, d_in, h):
+    feats, labels, p0, mean, istd, px = _setup(3, 300, d_in, h)
     n = len(feats)
     cls = torch.empty(n, dtype=torch.int8, device=device)
     conf = torch.empty(n, device=device)
