@@ -50,8 +50,9 @@ def main():
     ap.add_argument("--export-tuning", default=None, help="write the GEMM tuning table used to this file")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with plain 1 GiB device copies (calibration of HBM byte counters)")
-    ap.add_argument("--proxy-train", type=int, default=16384,
+    ap.add_argument("--proxy-train", type=int, default=50000,
                     help="documents the proxy is trained on (labels from the full BF16 r=1 operator)")
+    ap.add_argument("--proxy-eval", type=int, default=20000, help="fresh documents the proxy is evaluated on")
     ap.add_argument("--proxy-epochs", type=int, default=20)
     ap.add_argument("--no-proxy", action="store_true")
     ap.add_argument("--no-compression", action="store_true",
@@ -134,9 +135,9 @@ def main():
         tune_report = {"imported": os.path.basename(args.tuning)}
     else:
         tune_report = autotune(K, mb, [n * 32, 60000, n], "bf16")
-    proxy = None
+    proxy, proxy_info = None, None
     if not args.no_proxy:
-        proxy, proxy_info = train_proxy(K, synth, mb, shape, wl.suffix, args, dev)
+        proxy, proxy_info = train_proxy(K, synth, mb, shape, wl.suffix, args, dev, torch.cuda.current_stream())
     probe = K.kvop_pool_create(mb, K.KVOP_KV_BF16, 1 << 20)
     need = sum(K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths)
     K.kvop_pool_destroy(probe)
@@ -210,7 +211,7 @@ def main():
                 b += 1
             hf, tb = build(poolf, a, b)
             t_build32 += tb
-            ms, lg, dec = timed_eval(poolf, 1.0, hf, sel=(a, b), steps=1, warmup=0)
+            ms, lg, dec = timed_eval(poolf, 1.0, hf, sel=(a, b), steps=max(10, args.steps), warmup=args.warmup)
             ms_tot += ms
             logits32.append(lg)
             dec32.append(dec)
@@ -244,6 +245,9 @@ def main():
                 % (rows_main, 2 * shape.d_ffn, shape.d_model), "achieved": achieved,
                 "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
                 "launches": len(gu_big), "avg_launch_ms": gu_ms, "flops_per_launch": gu_flops}
+    tr_us = trace_launch_us()
+    roofline["frac_from_committed_trace"] = None if tr_us is None else gu_flops / (tr_us * 1e-6) / 1e12 / PEAK_BF16_TFLOPS
+    roofline["committed_trace_avg_launch_ms"] = None if tr_us is None else tr_us / 1e3
     att_ms, att_cnt = prof["attention"]
     k1 = int(docs.lengths.sum())
     att_bytes = (k1 + 32 * n) * 2 * shape.n_kv_heads * shape.head_dim * 2 * shape.n_layers
@@ -253,8 +257,11 @@ def main():
     value, step_ms, path = plain_value, headline_ms, "bf16 weights/activations, bf16 KV cache, no proxy"
     if cascade is not None:
         value, step_ms = cascade["tuples_per_s"], cascade["ms"]
-        path = (f"learned proxy (tau={cascade['tau']}) answers confident tuples, the full bf16 operator "
-                f"(bf16 KV cache, r=1) the rest")
+        path = (f"learned proxy (tau={cascade['tau']}) answers the tuples it is confident on "
+                f"({cascade['coverage']:.1%} of them), the full bf16 operator (bf16 KV cache, r=1) the rest; "
+                f"{value / plain_value - 1:+.1%} over the plain bf16 rate")
+    elif proxy_info is not None:
+        path += " (the trained proxy met no tau at <= 1% held-out disagreement and is not used)"
     line = {
         "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak",
@@ -269,7 +276,8 @@ def main():
         "attention_kernel": K.kvop_get_attention_kernel(),
         "gemm_tiles": tune_report,
         "bf16_plain_tuples_per_s": plain_value,
-        "proxy": cascade,
+        "proxy": cascade if cascade is not None else (None if proxy_info is None else
+                                                       {"used": False, "training": proxy_info}),
         "per_r": per_r,
         "compression": compression,
         "padded_batching": padded,
@@ -701,14 +709,17 @@ def autotune(K, model, rows_list, tag):
     return chosen
 
 
-def train_proxy(K, synth, mb, shape, suffix, args, dev):
-    """Build training documents in waves (pooled features from kv_build, labels from the
-    full BF16 r=1 filter), then train the proxy with Adam and pick tau on a held-out split."""
+TAUS = (0.9, 0.95, 0.99)
+
+
+def _proxy_waves(K, synth, mb, docs, suffix, dev, per_wave=None):
+    """Build the documents' caches in waves that fit HBM; for each wave write the pooled
+    features and the full BF16 r=1 operator's log-odds, call per_wave(a, b, pool, handles,
+    idx, ioffs, op, feats) while the caches are resident, then release them.  Returns
+    (features [n, d] on the device, log-odds [n])."""
     import torch
-    t0 = time.time()
-    docs = synth.make_docs_lognormal(args.proxy_train, 512, 64, 4096, shape.vocab, seed=0, stream=101)
     n = len(docs.lengths)
-    feats = torch.empty(n, shape.d_model, dtype=torch.float32, device=dev)
+    feats = torch.empty(n, synth.SCALE.d_model, dtype=torch.float32, device=dev)
     lo = np.empty(n, np.float64)
     probe = K.kvop_pool_create(mb, K.KVOP_KV_BF16, 1 << 20)
     sizes = [K.kvop_doc_bytes(probe, int(L)) for L in docs.lengths]
@@ -726,19 +737,38 @@ def train_proxy(K, synth, mb, shape, suffix, args, dev):
         offs = docs.offsets[a:b + 1] - docs.offsets[a]
         h = K.kvop_kv_build(pool, toks[int(docs.offsets[a]):int(docs.offsets[b])], offs, feats[a:b])
         idx, ioffs = synth.full_lists(docs.lengths[a:b])
+        idx = torch.from_numpy(idx).to(dev)
         lg = torch.empty(b - a, 2, dtype=torch.float32, device=dev)
-        K.kvop_op_eval(pool, op, 1.0, torch.from_numpy(idx).to(dev), ioffs, h, lg, None)
+        K.kvop_op_eval(pool, op, 1.0, idx, ioffs, h, lg, None)
         lgc = lg.cpu().numpy().astype(np.float64)
         lo[a:b] = lgc[:, 0] - lgc[:, 1]
+        if per_wave is not None:
+            per_wave(a, b, pool, h, idx, ioffs, op, feats)
         K.kvop_kv_release(pool, h)
-        log(f"proxy data [{a}, {b}) done at {time.time() - t0:.1f} s")
         a = b
     K.kvop_pool_destroy(pool)
-    del toks
+    return feats, lo
+
+
+def train_proxy(K, synth, mb, shape, suffix, args, dev, stream):
+    """The learned proxy at its full configuration: a 2048 -> 256 -> 2 MLP on pooled features,
+    trained on args.proxy_train seeded documents labelled by the full BF16 r = 1 operator
+    (a tenth held out for early stopping and the choice of tau), then evaluated on
+    args.proxy_eval fresh documents from another seed stream.  On the fresh documents, per
+    tau: coverage, disagreement with the full operator (over all tuples and over the
+    answered ones) and the timed rate of the cascade (proxy, then the full operator on the
+    tuples it leaves unsure) beside the full operator's own rate.  tau* is the smallest tau
+    whose held-out disagreement is at most 1%; if none qualifies the proxy is not used."""
+    import torch
+    t0 = time.time()
+    tr_docs, ev_docs = synth.proxy_split(0, n_train=args.proxy_train, n_eval=args.proxy_eval)
+    feats, lo = _proxy_waves(K, synth, mb, tr_docs, suffix, dev)
+    n = len(lo)
+    t_data = time.time() - t0
     labels_np = (lo > 0).astype(np.int32)
     pos_frac = float(labels_np.mean())
-    log(f"proxy labels: {pos_frac:.3f} accepted")
-    n_tr = int(n * 0.8)
+    log(f"proxy training data: {n} documents in {t_data:.1f} s, {pos_frac:.3f} accepted")
+    n_tr = n - n // 10
     labels = torch.from_numpy(labels_np).to(dev)
     p0 = synth.proxy_init(shape.d_model, 256, 2, 0)
     packed = np.concatenate([p0["w1"].ravel(), p0["b1"], p0["w2"].ravel(), p0["b2"]]).astype(np.float32)
@@ -760,11 +790,13 @@ def train_proxy(K, synth, mb, shape, suffix, args, dev):
         return float(-np.mean(np.log(np.maximum(p_true, 1e-12))))
 
     t1 = time.time()
+    history = []
     for ep in range(args.proxy_epochs):
         order = torch.from_numpy(synth.proxy_order(n_tr, ep, 0)).to(dev)
         for s0 in range(0, n_tr - bs + 1, bs):
             K.kvop_proxy_train_step(px, feats, labels, order[s0:s0 + bs], bs, 1e-3, loss)
         vl = val_loss()
+        history.append(round(vl, 5))
         if vl < best_loss:
             best_loss, best_ep = vl, ep
             K.kvop_proxy_params(px, best)
@@ -775,23 +807,81 @@ def train_proxy(K, synth, mb, shape, suffix, args, dev):
     K.kvop_proxy_destroy(px)
     px = K.kvop_proxy_create(shape.d_model, 256, best)
     K.kvop_proxy_fit_standardizer(px, feats[:n_tr])
-    # validation split: disagreement with the full operator among all tuples, per tau
     held = {}
     tau_star = None
-    for tau in (0.9, 0.95, 0.99):
+    for tau in TAUS:
         K.kvop_proxy_infer(px, feats[n_tr:], tau, cls, conf, ans)
         c, an = cls.cpu().numpy(), ans.cpu().numpy().astype(bool)
         dis = float(np.mean((c != labels_np[n_tr:]) & an))
         held[str(tau)] = {"coverage": float(an.mean()), "disagreement": dis}
         if tau_star is None and dis <= 0.01:
             tau_star = tau
+    log(f"proxy held-out: {held}, best epoch {best_ep}, tau* = {tau_star}")
+    del feats, labels
+    torch.cuda.empty_cache()
+    # fresh documents: labels and timed rates wave by wave (caches resident, not timed)
+    ne = len(ev_docs.lengths)
+    ev = {"full_ms": 0.0, "cascade_ms": {str(t): 0.0 for t in TAUS}}
+    ev_cls = {str(t): np.empty(ne, np.int8) for t in TAUS}
+    ev_ans = {str(t): np.empty(ne, bool) for t in TAUS}
+
+    def per_wave(a, b, pool, h, idx, ioffs, op, feats_ev):
+        m = b - a
+        lg = torch.empty(m, 2, dtype=torch.float32, device=dev)
+        dec = torch.empty(m, dtype=torch.int8, device=dev)
+        ev["full_ms"] += _timed(lambda: K.kvop_op_eval(pool, op, 1.0, idx, ioffs, h, lg, dec), stream)
+        c = torch.empty(m, dtype=torch.int8, device=dev)
+        cf = torch.empty(m, dtype=torch.float32, device=dev)
+        an = torch.empty(m, dtype=torch.int8, device=dev)
+        f = feats_ev[a:b]
+        for t in TAUS:
+            def cascade():
+                K.kvop_proxy_infer(px, f, t, c, cf, an)
+                sel = np.nonzero(an.cpu().numpy() == 0)[0].astype(np.int32)   # the host routes the unsure tuples
+                if len(sel):
+                    K.kvop_op_eval_select(pool, op, 1.0, idx, ioffs, h, sel, lg, dec)
+            ev["cascade_ms"][str(t)] += _timed(cascade, stream)
+            ev_cls[str(t)][a:b] = c.cpu().numpy()
+            ev_ans[str(t)][a:b] = an.cpu().numpy().astype(bool)
+
+    t2 = time.time()
+    feats_ev, lo_ev = _proxy_waves(K, synth, mb, ev_docs, suffix, dev, per_wave=per_wave)
+    del feats_ev
+    full_ev = (lo_ev > 0).astype(np.int8)
+    fresh = {"documents": ne, "label_accept_frac": float(full_ev.mean()),
+             "full_operator_tuples_per_s": ne / (ev["full_ms"] / 1e3), "per_tau": {}}
+    for t in TAUS:
+        k = str(t)
+        an, c = ev_ans[k], ev_cls[k]
+        wrong = (c != full_ev) & an
+        fresh["per_tau"][k] = {
+            "coverage": float(an.mean()), "disagreement_vs_full_operator": float(wrong.mean()),
+            "disagreement_among_answered": float(wrong.sum() / max(1, an.sum())),
+            "cascade_tuples_per_s": ne / (ev["cascade_ms"][k] / 1e3),
+            "gain_over_full_operator": ev["full_ms"] / ev["cascade_ms"][k]}
+    log(f"proxy on {ne} fresh documents ({time.time() - t2:.1f} s): {fresh}")
+    info = {"train_docs": n_tr, "heldout_docs": nh, "label_accept_frac": pos_frac, "train_s": t_train,
+            "epochs": args.proxy_epochs, "best_epoch": best_ep, "heldout_loss": best_loss, "loss_history": history,
+            "data_s": t_data, "heldout": held, "tau": tau_star, "fresh": fresh}
     if tau_star is None:
-        tau_star = 0.99
-    log(f"proxy validation: {held}, best epoch {best_ep}, tau* = {tau_star}")
-    info = {"train_docs": n_tr, "validation_docs": nh, "label_accept_frac": pos_frac, "train_s": t_train,
-            "best_epoch": best_ep, "validation_loss": best_loss,
-            "data_s": time.time() - t0 - t_train, "validation": held, "tau": tau_star}
+        log("no tau meets 1% held-out disagreement: the proxy is not used")
+        K.kvop_proxy_destroy(px)
+        px = None
     return px, info
+
+
+def _timed(fn, stream):
+    """ms of fn() on the stream (HIP events), or the host's clock if that is longer (fn may
+    synchronise on the host)."""
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.time()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return max(e0.elapsed_time(e1), (time.time() - t0) * 1e3)
 
 
 def time_cascade(K, px, info, pool, handles, pooled, lists, op, full_out, n, args, dev, stream):
@@ -862,6 +952,22 @@ def counted_traffic(tile):
         return None
 
 
+def trace_launch_us():
+    """Average gate/up launch duration from the committed rocprofv3 kernel trace, or None when
+    the GEMM source differs from the one the trace was taken on."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "filter4096_bf16_kernel_trace.md")
+    src = os.path.join(here, "paper_2602_04430_amd", "csrc", "gemm.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line
+                      and line.split(": ", 1)[0] in ("gate_up_trace_avg_us", "gemm_hip_sha256"))
+        same_src = hashlib.sha256(open(src, "rb").read()).hexdigest() == fields["gemm_hip_sha256"].strip()
+        return float(fields["gate_up_trace_avg_us"]) if same_src else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def copy_probe(dev):
     """Three plain device-to-device copies of 1 GiB: each reads and writes exactly 2^30 bytes,
     which calibrates the HBM byte counters (FETCH_SIZE, WRITE_SIZE) against known traffic."""
@@ -903,7 +1009,28 @@ def oracle_baseline(shape, w, docs, suffix, n_sample, gpu_bf16_logits, gpu_f32_l
             break
     t_eval = time.time() - t1
     ref = np.stack([r.logits for r in res])
+    # the same evaluation on one thread (BLAS limited to 1), a bounded number of evaluations
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t2 = time.time()
+            e1 = 0
+            while e1 < n_sample and time.time() - t2 < min_seconds:
+                om.filter_eval(m, caches[e1], np.arange(docs.lengths[e1]), suffix, synth.YES_ID, synth.NO_ID)
+                e1 += 1
+            one = {"value": e1 / (time.time() - t2), "evaluations": e1, "seconds": time.time() - t2}
+    except ImportError:
+        pass
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     out = {"value": evals / t_eval, "unit": "tuples/s", "cores": int(threads), "kind": "oracle",
+           "blas_threads": int(threads), "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model,
+           "one_thread": one,
            "sample": f"FP64 NumPy oracle filter evaluation (r=1) of the first {n_sample} of the 4096 documents "
                      f"(L={[int(x) for x in docs.lengths[:n_sample]]}), {evals // n_sample} passes, {evals} "
                      f"evaluations; caches built by the oracle beforehand ({t_build:.1f} s, not in the rate)",
