@@ -143,6 +143,7 @@ def main():
     K.kvop_pool_destroy(probe)
     free = torch.cuda.mem_get_info()[0]
     log(f"BF16 cache needs {need / 2**30:.1f} GiB, free {free / 2**30:.1f} GiB")
+    prof8 = None
     pool = K.kvop_pool_create(mb, K.KVOP_KV_BF16, need + (64 << 20))
     pooled = torch.empty(n, shape.d_model, dtype=torch.float32, device=dev)
     hb, t_build = build(pool, 0, n, pooled)
@@ -189,6 +190,10 @@ def main():
             per_r[str(r)]["bf16_fp8kv_tuples_per_s"] = n / (ms / 1e3)
             per_r[str(r)]["fp8kv_vs_bf16kv_decision_disagreement"] = float(np.mean(dec != bf16_out[r][1]))
             log(f"FP8 r={r}: {ms:.1f} ms/step")
+        K.kvop_profile_start()
+        timed_eval(pool8, 1.0, h8, steps=1)
+        prof8 = K.kvop_profile_stop()
+        log("profile FP8 cache, r = 1 (ms, launches):", {k: (round(v[0], 2), v[1]) for k, v in prof8.items()})
         K.kvop_pool_destroy(pool8)
     K.kvop_model_destroy(mb)
     # ------------------------------------------------------------------ FP32 plain path (waves)
@@ -252,7 +257,18 @@ def main():
     k1 = int(docs.lengths.sum())
     att_bytes = (k1 + 32 * n) * 2 * shape.n_kv_heads * shape.head_dim * 2 * shape.n_layers
     roof_att = {"bound": "hbm", "achieved": att_bytes / (att_ms / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": att_bytes / (att_ms / 1e3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": att_ms / max(1, att_cnt)}
+                "frac": att_bytes / (att_ms / 1e3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": att_ms / max(1, att_cnt),
+                "ms_per_step": att_ms}
+    roof_att8 = None
+    if prof8 is not None:
+        # FP8 cache rows (1 byte per element, FP32 scales per 16-row block) plus the 32 own
+        # rows per item in BF16, keys and values, 8 heads x 128, 16 layers
+        a8_ms, a8_cnt = prof8["attention"]
+        a8_bytes = (k1 * (shape.head_dim + 4 / 16) + 32 * n * shape.head_dim * 2) * 2 * shape.n_kv_heads * \
+            shape.n_layers
+        roof_att8 = {"bound": "hbm", "achieved": a8_bytes / (a8_ms / 1e3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": a8_bytes / (a8_ms / 1e3) / 1e9 / PEAK_HBM_GBS, "avg_launch_ms": a8_ms / max(1, a8_cnt),
+                     "ms_per_step": a8_ms, "bf16_cache_attention_ms_per_step": att_ms}
     plain_value = n / (headline_ms / 1e3)
     value, step_ms, path = plain_value, headline_ms, "bf16 weights/activations, bf16 KV cache, no proxy"
     if cascade is not None:
@@ -272,6 +288,7 @@ def main():
                    "docs": n, "sum_L": k1},
         "roofline": roofline,
         "roofline_attention": roof_att,
+        "roofline_attention_fp8_cache": roof_att8,
         "kernel_ms_per_step": {k: round(v[0], 3) for k, v in prof.items()},
         "attention_kernel": K.kvop_get_attention_kernel(),
         "gemm_tiles": tune_report,

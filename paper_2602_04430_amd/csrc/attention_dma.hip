@@ -46,8 +46,7 @@ struct DmaCfg {
   static constexpr int META = 3 * 64 * 4;            // ksc | vsc | unused (64 slots each)
   static constexpr int STAGE = 2 * REGION + META;
   static constexpr int RING = NS * STAGE;            // row-number ring: NS + 1 slots of 64
-  static constexpr int DESC = RING + (NS + 1) * 64 * 4;  // 3 source descriptors
-  static constexpr int LDS = DESC + 3 * 64;
+  static constexpr int LDS = RING + (NS + 1) * 64 * 4;
   static constexpr int LDS_TOTAL = LDS;
   // vmcnt that leaves only the newest tile's chunk + metadata loads outstanding
   static constexpr int WAIT = NS >= 3 ? NJ + 1 : 0;
@@ -134,14 +133,15 @@ struct __attribute__((aligned(8))) DmaSrc {
   int n, clampL, pos_add;
   int npad;             // keys iterated (>= n when padded, else n); keys past n are masked
 };
-static_assert(sizeof(DmaSrc) <= 64, "descriptor slot");
 
-template <typename TKV, int D, int KT, int NS>
+template <typename TKV, int D, int KT, int NS, int KC>
 __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
   using C = DmaCfg<TKV, D, KT, NS>;
   constexpr int NQ = D / 32;                 // 32-deep K steps of S^T
   constexpr int ND = D / 16;                 // 16-wide d blocks of the output
-  constexpr int NB = KT / 16;                // 16-key blocks of a cache tile
+  constexpr int NBC = KC / 16;               // 16-key blocks of one compute step
+  constexpr int NSTEP = KT / KC;             // compute steps per cache tile
+  static_assert(KT % KC == 0 && KC % 32 == 0, "compute steps of whole 32-key pairs");
   constexpr bool FP8 = C::FP8;
 
   const int Hkv = a.Hkv;
@@ -216,14 +216,6 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
   }
   const int TA = (src0.npad + KT - 1) / KT, TB = (src1.npad + KT - 1) / KT;
   const int TO = (src2.n + C::KTO - 1) / C::KTO;
-  // The three descriptors go to LDS once; the issuing and the computing side each keep a
-  // register copy of the current source and reload it from LDS when their tile index
-  // crosses into the next source (a runtime-selected local would live in scratch memory,
-  // and a scratch load waits behind every tile load in flight).
-  DmaSrc* ldsrc = reinterpret_cast<DmaSrc*>(smem + C::DESC);
-  if (tid == 0) ldsrc[0] = src0;
-  if (tid == 1) ldsrc[1] = src1;
-  if (tid == 2) ldsrc[2] = src2;
   vm_wait<0>();  // the query fragments have arrived (the loop's waits count tile loads only)
   __syncthreads();
   const int T = TA + TB + TO;
@@ -241,19 +233,22 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
   // slots: the loop then holds no register-destination memory load, so the only waits on
   // memory are the explicit ones below.  Ring slot of tile X: X % (NS + 1).
   int* ring = reinterpret_cast<int*>(smem + C::RING);
-  int iss_sidx = -1, cmp_sidx = -1;
-  DmaSrc iss = src0, cmp = src0;
-  auto issue_src = [&](int sidx) -> const DmaSrc& {
-    if (sidx != iss_sidx) {
-      iss = ldsrc[sidx];
-      iss_sidx = sidx;
-    }
-    return iss;
+  // The current source is selected field by field from the three descriptors, which are
+  // uniform across the workgroup and stay in scalar registers (an indexed local array
+  // would live in scratch memory, and a scratch load waits behind every tile load in
+  // flight).
+  auto pick = [&](int sidx) {
+    DmaSrc r;
+#define KVOP_PICK(f) r.f = sidx == 0 ? src0.f : (sidx == 1 ? src1.f : src2.f)
+    KVOP_PICK(k); KVOP_PICK(v); KVOP_PICK(pitch); KVOP_PICK(idx); KVOP_PICK(ksc); KVOP_PICK(vsc);
+    KVOP_PICK(n); KVOP_PICK(clampL); KVOP_PICK(pos_add); KVOP_PICK(npad);
+#undef KVOP_PICK
+    return r;
   };
   auto issue_rows = [&](int ti) {
     int sidx, t0;
     tile_src(ti, sidx, t0);
-    const DmaSrc& s = issue_src(sidx);
+    const DmaSrc s = pick(sidx);
     // a padded tile (past the source's keys) loads the source's rows again from the start
     // of the list, cyclically: real rows, so the padded keys cost loads and multiplies
     const int tl = t0 < s.n ? t0 : t0 % s.n;
@@ -266,7 +261,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
   auto issue_tile = [&](int ti, int st) {
     int sidx, t0;
     tile_src(ti, sidx, t0);
-    const DmaSrc& s = issue_src(sidx);
+    const DmaSrc s = pick(sidx);
     const int tl = t0 < s.n ? t0 : t0 % s.n;   // as in issue_rows
     const int* rws = ring + (ti % (NS + 1)) * 64;
     uint8_t* sb = smem + st * C::STAGE;
@@ -333,11 +328,7 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
 
     int sidx, t0;
     tile_src(ti, sidx, t0);
-    if (sidx != cmp_sidx) {
-      cmp = ldsrc[sidx];
-      cmp_sidx = sidx;
-    }
-    const DmaSrc& s = cmp;
+    const DmaSrc s = pick(sidx);
     const bool own = sidx == 2;
     const bool tile_fp8 = FP8 && !own;
     const int nbt = (own ? C::KTO : KT) / 16;  // 16-key blocks present in this tile
@@ -352,142 +343,151 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
     if (has_b && (ti == TA || ti == TA + TB)) load_q(ti == TA ? q_rot : q_plain);
     if (!wave_active) continue;
 
-    // ---- scores S^T[key][query]: lane holds keys 16 b + 4 g4 + t of query column qi
-    f32x4 sc[NB];
+    // The tile is computed in steps of KC keys (blocks kb0 .. kb0 + NBC - 1), each with its own
+    // online-softmax update: a tile may carry more keys than one step holds in registers.
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-      sc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (b >= nbt) continue;
-      const int kr = 16 * b + qi;
+    for (int hc = 0; hc < NSTEP; hc++) {
+      const int kb0 = hc * NBC;
+      if (kb0 >= nbt) break;
+      // ---- scores S^T[key][query]: lane holds keys 16 (kb0 + b) + 4 g4 + t of query column qi
+      f32x4 sc[NBC];
 #pragma unroll
-      for (int k = 0; k < NQ; k++) {
-        u32x4 kf;
-        if (tile_fp8) {
-          const int pc = 4 * k + g4;  // 8-byte piece of the FP8 row
-          const u32x2 raw = *reinterpret_cast<const u32x2*>(Kp + kr * C::RBC + ((pc >> 1) ^ swz_k<C::CHC>(kr)) * 16 +
-                                                           (pc & 1) * 8);
-          kf = fp8x8_to_bf16x8(raw[0], raw[1]);
-        } else if (own) {
-          kf = *reinterpret_cast<const u32x4*>(Kp + kr * C::RBO + ((4 * k + g4) ^ swz_k<C::CHO>(kr)) * 16);
-        } else {
-          kf = *reinterpret_cast<const u32x4*>(Kp + kr * C::RBC + ((4 * k + g4) ^ swz_k<C::CHC>(kr)) * 16);
-        }
-        sc[b] = mfma_bf16(__builtin_bit_cast(u16x8, kf), __builtin_bit_cast(u16x8, qf[k]), sc[b]);
-      }
-    }
-    // ---- online softmax (FP32).  Keys past the source's end and keys after the query's
-    // position are masked; only tiles that can hold such keys test positions.
-    const int n_here = s.n - t0;
-    const bool need_mask = own || n_here < nbt * 16 || (!s.idx && t0 + nbt * 16 - 1 + s.pos_add > w.q_pos0) ||
-                           (s.idx && rows_s[nbt * 16 - 1] + s.pos_add > w.q_pos0);
-    float mx = -INFINITY;
+      for (int b = 0; b < NBC; b++) {
+        sc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (kb0 + b >= nbt) continue;
+        const int kr = 16 * (kb0 + b) + qi;
 #pragma unroll
-    for (int b = 0; b < NB; b++)
-#pragma unroll
-      for (int t = 0; t < 4; t++) {
-        const int key = 16 * b + 4 * g4 + t;
-        float v = sc[b][t];
-        if (tile_fp8) v *= ksc_s[key];
-        if (b >= nbt) {
-          v = -INFINITY;
-        } else if (need_mask) {
-          const int kpos = key < n_here ? (s.idx ? rows_s[key] : t0 + key) + s.pos_add : 0x7fffffff;
-          if (!(kpos <= qpos)) v = -INFINITY;
-        }
-        sc[b][t] = v;
-        mx = fmaxf(mx, v);
-      }
-    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-    const float c = a.scale_log2;
-    const float m_new = fmaxf(m_run, mx);
-    const float mc = m_new == -INFINITY ? 0.f : m_new * c;
-    // rescale of the running sums: exactly 1 when the maximum did not move (the contracted
-    // m_run * c - mc is then the rounding error of mc, not 0), 0 when m_run = -inf
-    const float alpha = m_new > m_run ? __builtin_amdgcn_exp2f(m_run * c - mc) : 1.f;
-    float psum = 0.f;
-#pragma unroll
-    for (int b = 0; b < NB; b++)
-#pragma unroll
-      for (int t = 0; t < 4; t++) {
-        const float pv = __builtin_amdgcn_exp2f(fmaf(sc[b][t], c, -mc));  // exp2(-inf) = 0
-        sc[b][t] = pv;
-        psum += pv;
-      }
-    l_run = l_run * alpha + psum;
-    m_run = m_new;
-#pragma unroll
-    for (int i = 0; i < ND; i++) o[i] *= alpha;
-
-    // ---- O^T[d][query] += V^T[d][key] P^T[key][query].  K slots 0..3 of lane group g4 are
-    // keys 32 b2 + 4 g4 + t, slots 4..7 keys 32 b2 + 16 + 4 g4 + t.
-#pragma unroll
-    for (int b2 = 0; b2 < NB / 2; b2++) {
-      if (2 * b2 >= nbt) continue;
-      u32x4 pb;
-#pragma unroll
-      for (int t = 0; t < 4; t += 2) {
-        float p0 = sc[2 * b2][t], p0n = sc[2 * b2][t + 1];
-        float p1 = sc[2 * b2 + 1][t], p1n = sc[2 * b2 + 1][t + 1];
-        if (tile_fp8) {
-          p0 *= vsc_s[32 * b2 + 4 * g4 + t];
-          p0n *= vsc_s[32 * b2 + 4 * g4 + t + 1];
-          p1 *= vsc_s[32 * b2 + 16 + 4 * g4 + t];
-          p1n *= vsc_s[32 * b2 + 16 + 4 * g4 + t + 1];
-        }
-        pb[t / 2] = pack_bf16x2(p0, p0n);
-        pb[2 + t / 2] = pack_bf16x2(p1, p1n);
-      }
-      // lane (qi, g4) reads V[keys 32 b2 + 4 g4 + 0..3 (+16)][d = 16 i + qi].  A tile with a
-      // single 16-key block in this pair (a 16-key own tile) has no rows +16: those keys
-      // carry p = 0, so any finite row will do (the tile's own rows, not bytes past it)
-      const int vr0 = 32 * b2 + 4 * g4 + (qi >> 2), vr1 = 2 * b2 + 1 < nbt ? vr0 + 16 : vr0;
-      if (tile_fp8) {
-        // 8-bit transposed reads: within a lane group, lane qi addresses key slot qi / 2
-        // (row 32 b2 + 4 g4 + (qi/2 < 4 ? qi/2 : 16 + qi/2 - 4)) at byte columns
-        // 16 i + 8 (qi % 2) .. +7; lane qi receives byte column 16 i + qi of the 8 rows
-        const int ks = qi >> 1;
-        const int vr = 32 * b2 + 4 * g4 + (ks < 4 ? ks : 12 + ks);
-        const int sv = swz_v8<C::CHC>(vr);
-        u32x2 y[ND];
-#pragma unroll
-        for (int i = 0; i < ND; i++) y[i] = ds_read_tr8(Vp + vr * C::RBC + ((i ^ sv) * 16) + (qi & 1) * 8);
-        lgkm_wait_all<ND>(y);
-#pragma unroll
-        for (int i = 0; i < ND; i++) {
-          const u32x4 va = fp8x8_to_bf16x8(y[i][0], y[i][1]);
-          o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
-        }
-      } else {
-        // 16-bit transposed reads: lane (qi, g4) addresses row vr (qi / 4 selects the key),
-        // columns 16 i + 4 (qi % 4) .. +3; lane qi receives column 16 i + qi of 4 rows
-        const int rb = own ? C::RBO : C::RBC;
-        const int s0 = own ? swz_v<C::CHO>(vr0) : swz_v<C::CHC>(vr0);
-        const int s1 = own ? swz_v<C::CHO>(vr1) : swz_v<C::CHC>(vr1);
-        // 32-key tiles: in two halves of the d blocks (fewer live registers, for the
-        // register budget of three resident workgroups)
-        constexpr int NHALF = KT == 32 ? 2 : 1;
-#pragma unroll
-        for (int h2 = 0; h2 < NHALF; h2++) {
-          constexpr int NH = ND / NHALF;
-          u32x2 y[2 * NH];
-#pragma unroll
-          for (int ii = 0; ii < NH; ii++) {
-            const int i = h2 * NH + ii;
-            const int cch = (16 * i + 4 * (qi & 3)) >> 3, half = qi & 1;
-            y[2 * ii] = ds_read_tr16(Vp + vr0 * rb + (cch ^ s0) * 16 + half * 8);
-            y[2 * ii + 1] = ds_read_tr16(Vp + vr1 * rb + (cch ^ s1) * 16 + half * 8);
+        for (int k = 0; k < NQ; k++) {
+          u32x4 kf;
+          if (tile_fp8) {
+            const int pc = 4 * k + g4;  // 8-byte piece of the FP8 row
+            const u32x2 raw = *reinterpret_cast<const u32x2*>(Kp + kr * C::RBC + ((pc >> 1) ^ swz_k<C::CHC>(kr)) * 16 +
+                                                             (pc & 1) * 8);
+            kf = fp8x8_to_bf16x8(raw[0], raw[1]);
+          } else if (own) {
+            kf = *reinterpret_cast<const u32x4*>(Kp + kr * C::RBO + ((4 * k + g4) ^ swz_k<C::CHO>(kr)) * 16);
+          } else {
+            kf = *reinterpret_cast<const u32x4*>(Kp + kr * C::RBC + ((4 * k + g4) ^ swz_k<C::CHC>(kr)) * 16);
           }
-          lgkm_wait_all<2 * NH>(y);
+          sc[b] = mfma_bf16(__builtin_bit_cast(u16x8, kf), __builtin_bit_cast(u16x8, qf[k]), sc[b]);
+        }
+      }
+      // ---- online softmax (FP32).  Keys past the source's end and keys after the query's
+      // position are masked; only tiles that can hold such keys test positions.
+      const int n_here = s.n - t0;
+      const bool need_mask = own || n_here < nbt * 16 || (!s.idx && t0 + nbt * 16 - 1 + s.pos_add > w.q_pos0) ||
+                             (s.idx && rows_s[nbt * 16 - 1] + s.pos_add > w.q_pos0);
+      float mx = -INFINITY;
 #pragma unroll
-          for (int ii = 0; ii < NH; ii++) {
-            const int i = h2 * NH + ii;
-            const u32x4 va = u32x4{y[2 * ii][0], y[2 * ii][1], y[2 * ii + 1][0], y[2 * ii + 1][1]};
+      for (int b = 0; b < NBC; b++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int key = 16 * (kb0 + b) + 4 * g4 + t;
+          float v = sc[b][t];
+          if (tile_fp8) v *= ksc_s[key];
+          if (kb0 + b >= nbt) {
+            v = -INFINITY;
+          } else if (need_mask) {
+            const int kpos = key < n_here ? (s.idx ? rows_s[key] : t0 + key) + s.pos_add : 0x7fffffff;
+            if (!(kpos <= qpos)) v = -INFINITY;
+          }
+          sc[b][t] = v;
+          mx = fmaxf(mx, v);
+        }
+      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      const float c = a.scale_log2;
+      const float m_new = fmaxf(m_run, mx);
+      const float mc = m_new == -INFINITY ? 0.f : m_new * c;
+      // rescale of the running sums: exactly 1 when the maximum did not move (the contracted
+      // m_run * c - mc is then the rounding error of mc, not 0), 0 when m_run = -inf
+      const float alpha = m_new > m_run ? __builtin_amdgcn_exp2f(m_run * c - mc) : 1.f;
+      float psum = 0.f;
+#pragma unroll
+      for (int b = 0; b < NBC; b++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const float pv = __builtin_amdgcn_exp2f(fmaf(sc[b][t], c, -mc));  // exp2(-inf) = 0
+          sc[b][t] = pv;
+          psum += pv;
+        }
+      l_run = l_run * alpha + psum;
+      m_run = m_new;
+#pragma unroll
+      for (int i = 0; i < ND; i++) o[i] *= alpha;
+
+      // ---- O^T[d][query] += V^T[d][key] P^T[key][query].  K slots 0..3 of lane group g4 are
+      // keys 32 b2 + 4 g4 + t, slots 4..7 keys 32 b2 + 16 + 4 g4 + t (b2: pair of the tile;
+      // bl: the same pair's first block within this step).
+#pragma unroll
+      for (int bp = 0; bp < NBC / 2; bp++) {
+        const int bl = 2 * bp, b2 = kb0 / 2 + bp;
+        if (2 * b2 >= nbt) continue;
+        u32x4 pb;
+#pragma unroll
+        for (int t = 0; t < 4; t += 2) {
+          float p0 = sc[bl][t], p0n = sc[bl][t + 1];
+          float p1 = sc[bl + 1][t], p1n = sc[bl + 1][t + 1];
+          if (tile_fp8) {
+            p0 *= vsc_s[32 * b2 + 4 * g4 + t];
+            p0n *= vsc_s[32 * b2 + 4 * g4 + t + 1];
+            p1 *= vsc_s[32 * b2 + 16 + 4 * g4 + t];
+            p1n *= vsc_s[32 * b2 + 16 + 4 * g4 + t + 1];
+          }
+          pb[t / 2] = pack_bf16x2(p0, p0n);
+          pb[2 + t / 2] = pack_bf16x2(p1, p1n);
+        }
+        // lane (qi, g4) reads V[keys 32 b2 + 4 g4 + 0..3 (+16)][d = 16 i + qi].  A tile with a
+        // single 16-key block in this pair (a 16-key own tile) has no rows +16: those keys
+        // carry p = 0, so any finite row will do (the tile's own rows, not bytes past it)
+        const int vr0 = 32 * b2 + 4 * g4 + (qi >> 2), vr1 = 2 * b2 + 1 < nbt ? vr0 + 16 : vr0;
+        if (tile_fp8) {
+          // 8-bit transposed reads: within a lane group, lane qi addresses key slot qi / 2
+          // (row 32 b2 + 4 g4 + (qi/2 < 4 ? qi/2 : 16 + qi/2 - 4)) at byte columns
+          // 16 i + 8 (qi % 2) .. +7; lane qi receives byte column 16 i + qi of the 8 rows
+          const int ks = qi >> 1;
+          const int vr = 32 * b2 + 4 * g4 + (ks < 4 ? ks : 12 + ks);
+          const int sv = swz_v8<C::CHC>(vr);
+          u32x2 y[ND];
+#pragma unroll
+          for (int i = 0; i < ND; i++) y[i] = ds_read_tr8(Vp + vr * C::RBC + ((i ^ sv) * 16) + (qi & 1) * 8);
+          lgkm_wait_all<ND>(y);
+#pragma unroll
+          for (int i = 0; i < ND; i++) {
+            const u32x4 va = fp8x8_to_bf16x8(y[i][0], y[i][1]);
             o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
           }
+        } else {
+          // 16-bit transposed reads: lane (qi, g4) addresses row vr (qi / 4 selects the key),
+          // columns 16 i + 4 (qi % 4) .. +3; lane qi receives column 16 i + qi of 4 rows
+          const int rb = own ? C::RBO : C::RBC;
+          const int s0 = own ? swz_v<C::CHO>(vr0) : swz_v<C::CHC>(vr0);
+          const int s1 = own ? swz_v<C::CHO>(vr1) : swz_v<C::CHC>(vr1);
+          // 32-key tiles: in two halves of the d blocks (fewer live registers, for the
+          // register budget of three resident workgroups)
+          constexpr int NHALF = KC == 32 ? 2 : 1;
+#pragma unroll
+          for (int h2 = 0; h2 < NHALF; h2++) {
+            constexpr int NH = ND / NHALF;
+            u32x2 y[2 * NH];
+#pragma unroll
+            for (int ii = 0; ii < NH; ii++) {
+              const int i = h2 * NH + ii;
+              const int cch = (16 * i + 4 * (qi & 3)) >> 3, half = qi & 1;
+              y[2 * ii] = ds_read_tr16(Vp + vr0 * rb + (cch ^ s0) * 16 + half * 8);
+              y[2 * ii + 1] = ds_read_tr16(Vp + vr1 * rb + (cch ^ s1) * 16 + half * 8);
+            }
+            lgkm_wait_all<2 * NH>(y);
+#pragma unroll
+            for (int ii = 0; ii < NH; ii++) {
+              const int i = h2 * NH + ii;
+              const u32x4 va = u32x4{y[2 * ii][0], y[2 * ii][1], y[2 * ii + 1][0], y[2 * ii + 1][1]};
+              o[i] = mfma_bf16(__builtin_bit_cast(u16x8, va), __builtin_bit_cast(u16x8, pb), o[i]);
+            }
+          }
         }
       }
-    }
+    }  // steps
   }
 
   // ---- normalise and store: lane holds O[query qi][d = 16 i + 4 g4 + t]
@@ -508,19 +508,20 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
 }
 
 // One workgroup per unit.
-// 32-key tiles fit three workgroups' rings in LDS; the register budget is capped to match
-template <typename TKV, int D, int KT, int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KT == 32 ? 3 : 1)))
+// 32-key compute steps keep three workgroups' registers per CU (and their tiles fit LDS);
+// the register budget is capped to match
+template <typename TKV, int D, int KT, int NS, int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 3 : 1)))
 void attn_dma_kernel(AttnArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
-  attn_dma_unit<TKV, D, KT, NS>(a, blockIdx.x, dma_smem);
+  attn_dma_unit<TKV, D, KT, NS, KC>(a, blockIdx.x, dma_smem);
 }
 
 // Persistent form: a fixed grid takes units from a device counter (zeroed by the caller
 // before the launch) until every unit is taken; every workgroup exits once the counter
 // passes the unit count, so the grid always drains.
-template <typename TKV, int D, int KT, int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KT == 32 ? 3 : 1)))
+template <typename TKV, int D, int KT, int NS, int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 3 : 1)))
 void attn_dma_persistent_kernel(AttnArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
   __shared__ int next;
@@ -531,34 +532,37 @@ void attn_dma_persistent_kernel(AttnArgs a) {
     const int unit = next;
     __syncthreads();
     if (unit >= total) break;
-    attn_dma_unit<TKV, D, KT, NS>(a, unit, dma_smem);
+    attn_dma_unit<TKV, D, KT, NS, KC>(a, unit, dma_smem);
   }
 }
 
-template <typename TKV, int D, int KT, int NS>
+template <typename TKV, int D, int KT, int NS, int KC = KT>
 static hipError_t launch_dma(const AttnArgs& a, hipStream_t st) {
   using C = DmaCfg<TKV, D, KT, NS>;
   const int64_t units = (int64_t)a.n_work * a.Hkv;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)attn_dma_kernel<TKV, D, KT, NS>,
+    hipError_t e = hipFuncSetAttribute((const void*)attn_dma_kernel<TKV, D, KT, NS, KC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_TOTAL);
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)attn_dma_persistent_kernel<TKV, D, KT, NS>,
+      e = hipFuncSetAttribute((const void*)attn_dma_persistent_kernel<TKV, D, KT, NS, KC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS_TOTAL);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   if (a.counter) {
-    hipLaunchKernelGGL((attn_dma_persistent_kernel<TKV, D, KT, NS>),
+    hipLaunchKernelGGL((attn_dma_persistent_kernel<TKV, D, KT, NS, KC>),
                        dim3((unsigned)std::min<int64_t>(units, a.persistent_wgs)), dim3(256), C::LDS_TOTAL, st, a);
   } else {
-    hipLaunchKernelGGL((attn_dma_kernel<TKV, D, KT, NS>), dim3((unsigned)units), dim3(256), C::LDS_TOTAL, st, a);
+    hipLaunchKernelGGL((attn_dma_kernel<TKV, D, KT, NS, KC>), dim3((unsigned)units), dim3(256), C::LDS_TOTAL, st, a);
   }
   return hipGetLastError();
 }
 
-// variant: 0 = KT 64 / 2 stages, 1 = KT 64 / 3 stages, 2 = KT 32 / 3 stages
+// variant: 0 = KT 64 / 2 stages, 1 = KT 64 / 3 stages, 2 = 32-key compute steps / 3 stages
+// with 16 KiB of keys and values per stage: 32-key tiles of a BF16 cache, 64-key tiles of an
+// FP8 cache (its rows are half as long, so the tile moves the same bytes and a workgroup
+// keeps as many bytes in flight), each computed as two 32-key steps.
 // (D = 64 has no 32-key variant: its FP8 tile would be under one chunk load per thread)
 template <typename TKV, int D>
 static hipError_t launch_dma_variant(int variant, const AttnArgs& a, hipStream_t st) {
@@ -566,7 +570,8 @@ static hipError_t launch_dma_variant(int variant, const AttnArgs& a, hipStream_t
   if constexpr (D == 64) return launch_dma<TKV, D, 64, 3>(a, st);
   else {
     if (variant == 1) return launch_dma<TKV, D, 64, 3>(a, st);
-    return launch_dma<TKV, D, 32, 3>(a, st);
+    if constexpr (sizeof(TKV) == 1) return launch_dma<TKV, D, 64, 3, 32>(a, st);
+    else return launch_dma<TKV, D, 32, 3>(a, st);
   }
 }
 
