@@ -484,6 +484,22 @@ def bench_mixed(args, K, synth, dev):
     K.kvop_pool_destroy(pool)
     K.kvop_model_destroy(mb)
     ms = t_mode["graph_persistent"]
+    # summed roofline bound of the mix (r = 1, BF16 cache): per item, its projections at the
+    # BF16 MFMA peak (1.510 GFLOP per suffix row, 32 rows; a map adds 7 decode rows and its
+    # slice head) plus the keys/values its attention must read at 8 TB/s (65 536 bytes per
+    # row: 16 layers x 8 kv heads x 128 x K and V x 2 bytes): a filter reads L + 32 rows, a join
+    # L_A + L_B + 32, a map L + 32 for the suffix and L + 32 + t at decode step t = 1..7
+    gf_row = shape.gemm_flops_per_token()
+    kv_row = shape.kv_elems_per_token() * 2
+    Lf = docs.lengths[fdocs].astype(np.float64)
+    Lm = docs.lengths[mdocs].astype(np.float64)
+    Lj = (docs.lengths[pairs[:, 0]] + docs.lengths[pairs[:, 1]]).astype(np.float64)
+    flops = gf_row * 32 * (len(Lf) + len(Lm) + len(Lj)) + len(Lm) * (n_gen - 1) * (gf_row + 2 * shape.d_model * nl)
+    kv_bytes = kv_row * (np.sum(Lf + 32) + np.sum(Lj + 32) + np.sum(Lm + 32) +
+                         np.sum([np.sum(Lm + 32 + t) for t in range(1, n_gen)]))
+    bound_ms = (flops / (PEAK_BF16_TFLOPS * 1e12) + kv_bytes / (PEAK_HBM_GBS * 1e9)) * 1e3
+    roof = {"bound": "mfma+hbm (summed per item)", "bound_ms": bound_ms, "gemm_tflop": flops / 1e12,
+            "kv_gb": kv_bytes / 1e9, "frac_by_mode": {k: bound_ms / v for k, v in t_mode.items()}}
     line = {"metric": "tuples/sec mixed filter/map/join, one pass per wave (batching form)",
             "value": n_items / (ms / 1e3), "unit": "items/s", "n_gpus": 1, "steps": 1, "warmup": 1,
             "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
@@ -494,7 +510,7 @@ def bench_mixed(args, K, synth, dev):
             "modes_items_per_s": {k: n_items / (v / 1e3) for k, v in t_mode.items()},
             "differences_from_graph_mode": diff, "wave_rows": WAVE_ROWS, "small_waves": small,
             "profile_group0_ms": {"eager_mixed": prof_mixed, "separate_calls": prof_sep},
-            "kv_build_s": t_build, "gemm_tiles": tiles}
+            "kv_build_s": t_build, "gemm_tiles": tiles, "roofline_summed_bound": roof}
     print(json.dumps(line), flush=True)
 
 
