@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
                                                        float* __restrict__ logits, int64_t ldl,
                                                        int32_t* __restrict__ tok_out, int64_t ldt,
                                                        int32_t* __restrict__ next_tok, bool next_by_out) {
-  extern __shared__ float ysm[];       // d floats, then n logits
+  extern __shared__ __attribute__((aligned(16))) float ysm[];   // d floats, then n logits
   __shared__ float red[4];
   __shared__ int redi[4];
   int item = blockIdx.x;
@@ -427,12 +427,30 @@ __global__ __launch_bounds__(256) void head_map_kernel(const float* __restrict__
   for (int c = threadIdx.x; c < d; c += 256) ysm[c] = xr[c] * inv * g[c];
   __syncthreads();
   float* zl = ysm + d;
-  for (int j = wv; j < n; j += 4) {           // one wavefront per head row
-    const T* wr = W + (int64_t)(lo + j) * d;
-    float a = 0.f;
-    for (int c = lane; c < d; c += 64) a += ysm[c] * to_f32(wr[c]);
-    a = wave_sum(a);
-    if (lane == 0) zl[j] = a;
+  // four head rows per wavefront at a time, eight consecutive values per lane and load, so
+  // that a lane keeps four independent 16-byte (BF16) loads in flight per step
+  for (int j0 = 4 * wv; j0 < n; j0 += 16) {
+    float a[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int c = 8 * lane; c < d; c += 512) {
+      float yv[8], wvv[4][8];
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (j0 + q < n) Vec8<T>::load(W + (int64_t)(lo + j0 + q) * d + c, wvv[q]);
+      const f32x4 y0 = *reinterpret_cast<const f32x4*>(ysm + c), y1 = *reinterpret_cast<const f32x4*>(ysm + c + 4);
+#pragma unroll
+      for (int t = 0; t < 4; t++) { yv[t] = y0[t]; yv[4 + t] = y1[t]; }
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (j0 + q < n) {
+#pragma unroll
+          for (int t = 0; t < 8; t++) a[q] += yv[t] * wvv[q][t];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const float v = wave_sum(a[q]);
+      if (lane == 0 && j0 + q < n) zl[j0 + q] = v;
+    }
   }
   __syncthreads();
   // argmax, lowest index on ties
@@ -467,6 +485,7 @@ hipError_t head_map(int dt, const float* x, int64_t ldx, int n_items, int d, con
                     int64_t ld_logits, int32_t* tok_out, int64_t ld_tok, int32_t* next_tok, bool next_by_out,
                     hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
+  if (d % 8) return hipErrorInvalidValue;     // eight-value row pieces
   size_t lds = (size_t)(d + n) * sizeof(float);
   if (dt == DT_F32)
     hipLaunchKernelGGL(head_map_kernel<float>, dim3(n_items), dim3(256), lds, st, x, ldx, d, g, eps, (const float*)head,
