@@ -1526,6 +1526,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
       lp.attn.Pmax = Pmax;
       lp.attn.counter = persistent ? counter : nullptr;
       lp.attn.persistent_wgs = 2 * m->n_cu;
+      lp.attn.n_cu = m->n_cu;
       lp.own_from_qkv = true;
       for (int l = 0; l < c.n_layers; l++) {
         // the last layer continues with each operator's last suffix rows only (one strided
@@ -1693,6 +1694,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
         a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
         a.counter = persistent ? counter : nullptr;
         a.persistent_wgs = 2 * m->n_cu;
+        a.n_cu = m->n_cu;
         if (a.counter) HIPTRY(fill_i32(a.counter, 0, 1, st));
         HIPTRY(attention(m->dt, p->kvdt, D, a, st));
         {

@@ -551,8 +551,17 @@ static hipError_t launch_dma(const AttnArgs& a, hipStream_t st) {
     attr_set = true;
   }
   if (a.counter) {
+    // as many workgroups as are resident at once (registers and LDS decide: three per CU for
+    // the 32-key compute steps); each takes units until the counter passes their number
+    static int per_cu = 0;
+    if (per_cu == 0) {
+      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, (const void*)attn_dma_persistent_kernel<TKV, D, KT, NS, KC>, 256, C::LDS_TOTAL);
+      if (e != hipSuccess || per_cu < 1) per_cu = 2;
+    }
+    const int64_t wgs = (int64_t)per_cu * std::max(a.n_cu, 1);
     hipLaunchKernelGGL((attn_dma_persistent_kernel<TKV, D, KT, NS, KC>),
-                       dim3((unsigned)std::min<int64_t>(units, a.persistent_wgs)), dim3(256), C::LDS_TOTAL, st, a);
+                       dim3((unsigned)std::min<int64_t>(units, wgs)), dim3(256), C::LDS_TOTAL, st, a);
   } else {
     hipLaunchKernelGGL((attn_dma_kernel<TKV, D, KT, NS, KC>), dim3((unsigned)units), dim3(256), C::LDS_TOTAL, st, a);
   }

@@ -70,7 +70,9 @@ struct AttnArgs {
   int layer, n_layers, Hkv, G, Pmax;
   float scale_log2;    // log2(e) / sqrt(D)
   int* counter;        // persistent launch: unit counter (zeroed before the launch), else null
-  int persistent_wgs;  // persistent launch: number of workgroups
+  int persistent_wgs;  // persistent launch: number of workgroups (register-staged kernel)
+  int n_cu;            // persistent launch: compute units; the direct-load kernels launch as
+                       // many workgroups as fit on them at once
 };
 // cdt: compute/query dtype (f32 or bf16); kvdt: cache dtype (f32 with f32; bf16/fp8 with bf16)
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st);
