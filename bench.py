@@ -61,6 +61,10 @@ def main():
                     help="filter: the plain filter at scale (default); mixed: filter/map/join in one pass")
     ap.add_argument("--no-padded", action="store_true", help="skip the padded-batching ablation")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--rs", type=float, nargs="*", default=None,
+                    help="retention values to time besides r = 1 (default: the whole grid 1, 0.5, 0.25, 0.1)")
+    ap.add_argument("--attention-variant", type=int, default=None,
+                    help="attention kernel variant for the BF16/FP8 caches (default: the library's)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the operator path has no multi-GPU mode (run with --gpus 1)",
@@ -74,11 +78,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.attention_variant is not None:
+        K.kvop_set_attention_kernel(args.attention_variant)
     if args.workload == "mixed":
         return bench_mixed(args, K, synth, dev)
     shape = synth.SCALE
     t0 = time.time()
     wl = synth.scale_filter(0, n=args.n)
+    if args.rs:
+        # a subset of the retention grid (profiling runs); r = 1 always stays in
+        keep = tuple(r for r in wl.r_grid if r == 1.0 or r in args.rs)
+        wl = synth.Workload(wl.name, wl.shape, wl.docs, wl.suffix, keep, wl.extra)
     docs = wl.docs
     n = len(docs.lengths)
     log(f"workload: {n} docs, sum L = {int(docs.lengths.sum())}, mean L = {docs.lengths.mean():.1f}")
