@@ -383,7 +383,7 @@ def bench_mixed(args, K, synth, dev):
     sizes = [len(np.array_split(x, G)[0]) for x in (fdocs, mdocs, pairs)]
     n_waves = -(-32 * sum(sizes) // WAVE_ROWS)
     per = [-(-x // n_waves) for x in sizes]
-    tiles = autotune(K, mb, sorted({32 * sum(per), per[0], per[2]}), "bf16")
+    tiles = autotune(K, mb, sorted({32 * sum(per), per[0], per[1], per[2], sizes[1]}), "bf16")
     stream = torch.cuda.current_stream()
     modes = {"graph_persistent": K.KVOP_MIXED_PERSISTENT | K.KVOP_MIXED_GRAPH,
              "persistent": K.KVOP_MIXED_PERSISTENT, "eager": 0}
