@@ -4,6 +4,8 @@ The decoder is the 16-layer d_model-2048 model (16 query / 8 kv heads of 128, Sw
 vocab 32000, normal(0, 0.02) weights, seed 0).  Nothing here calls the GPU library.
 
   python -m tests.golden.make_scale_golden filter   # scale_filter_oracle.txt, scale_ea_scores.txt
+  python -m tests.golden.make_scale_golden fp8w     # scale_filter_oracle_fp8w.txt
+  python -m tests.golden.make_scale_golden bf16fp8  # scale_filter_oracle_bf16fp8.txt
   python -m tests.golden.make_scale_golden mixed    # mixed_sample_oracle.txt
 
 filter: 64 documents of the 4096-document filter workload (lognormal lengths, median 512, in
@@ -17,7 +19,12 @@ filter: 64 documents of the 4096-document filter workload (lognormal lengths, me
               and output, the rotated queries, the cached keys/values, the unnormalised
               probabilities and the attention output rounded to BF16)
     fp8fmt    the oracle whose cache holds the FP8-E4M3 format (16-row blocks with FP32 scales)
-  and the expected-attention row scores of three short documents under the BF16 form.
+  and the expected-attention row scores of three short documents under the BF16 form.  Two
+  more oracles of the same documents (files of their own, written by separate runs) serve the
+  FP8 cache's bound:
+    fp8w      the FP8-format oracle with the weights rounded to BF16
+    bf16fp8   the float64 emulation of the BF16 form whose cache holds the FP8 format (the
+              BF16-rounded projections' keys and values, rotated, quantised to FP8 blocks)
 mixed: items of the mixed-operator workload (16384 documents, lognormal median 384 in
   [16, 8192]; filter / map / join thirds; 2048 pairs) that every grouping of the benchmark
   with at most four groups places in its first group: 8 filter documents, 8 map documents and
@@ -45,6 +52,11 @@ N_FILTER_SAMPLE = 64
 EA_SAMPLE = [81, 100, 7]          # L = 64, 149, 123
 MIXED_FIRST_GROUP = 4             # items every grouping into <= 4 groups puts in group 0
 VARIANTS = ("fp64", "bf16w", "bf16form", "fp8fmt")
+FP8_VARIANTS = ("fp8w", "bf16fp8")
+
+
+def variant_file(var):
+    return os.path.join(HERE, f"scale_filter_oracle_{var}.txt")
 
 
 def filter_sample(lengths, n=N_FILTER_SAMPLE):
@@ -126,6 +138,39 @@ def make_filter():
     print("wrote", FILTER_FILE, EA_FILE, flush=True)
 
 
+def make_filter_variant(var):
+    """One extra oracle of the 64 sampled filter documents (fp8w or bf16fp8)."""
+    shape = synth.SCALE
+    wl = synth.scale_filter(0)
+    docs = wl.docs
+    w = synth.make_weights(shape, 0)
+    wb = {k: (codecs.bf16_round(v) if v.ndim == 2 else v).astype(np.float64) for k, v in w.items()}
+    del w
+    m = om.Model(shape, wb, act=codecs.bf16_round if var == "bf16fp8" else None)
+    lists = {r: synth.retained_lists(docs.lengths, r, seed=0) for r in wl.r_grid}
+    path = variant_file(var)
+    part = path + ".partial"
+    done = _done_keys(part, 4)
+    with open(part, "a") as fh:
+        if not done:
+            fh.write("# written by tests/golden/make_scale_golden.py (FP64 oracle only); "
+                     "columns: document L r variant logit_yes logit_no\n")
+        for i in filter_sample(docs.lengths):
+            L = int(docs.lengths[i])
+            if all((str(i), str(L), str(r), var) in done for r in wl.r_grid):
+                continue
+            t0 = time.time()
+            c = om.kv_build(m, docs.doc(i), store=codecs.fp8_cache_roundtrip)
+            for r in wl.r_grid:
+                idx, offs = lists[r]
+                res = om.filter_eval(m, c, idx[offs[i]:offs[i + 1]], wl.suffix, synth.YES_ID, synth.NO_ID)
+                fh.write(f"{i} {L} {r} {var} {res.logits[0]:.17g} {res.logits[1]:.17g}\n")
+            fh.flush()
+            print(f"filter document {i} L {L} {var}: {time.time() - t0:.1f} s", flush=True)
+    os.replace(part, path)
+    print("wrote", path, flush=True)
+
+
 def make_mixed():
     shape = synth.SCALE
     wl = synth.mixed_batch(0)
@@ -183,9 +228,12 @@ def make_mixed():
 
 
 def main():
-    what = sys.argv[1:] or ["filter", "mixed"]
+    what = sys.argv[1:] or ["filter", "fp8w", "bf16fp8", "mixed"]
     for w in what:
-        {"filter": make_filter, "mixed": make_mixed}[w]()
+        if w in FP8_VARIANTS:
+            make_filter_variant(w)
+        else:
+            {"filter": make_filter, "mixed": make_mixed}[w]()
     return 0
 
 

@@ -80,11 +80,16 @@ def test_bound_derivation_on_constructed_values():
         ref[(d, r, "bf16w")] = o + 0.01
         ref[(d, r, "bf16form")] = o + 0.01 + np.array([0.02, -0.03])
         ref[(d, r, "fp8fmt")] = o + 0.1
+        ref[(d, r, "fp8w")] = o + 0.11
+        ref[(d, r, "bf16fp8")] = o + 0.11 + np.array([0.05, 0.0])
     rows, b = sb.derive(ref)
     # N = |emulation - BF16 weights| = 0.03, F = |emulation - oracle| = |(0.03, -0.02)| = 0.03
     assert b["max_N"] == pytest.approx(0.03) and b["max_F"] == pytest.approx(0.03)
     assert b["E_bf16_form"] == pytest.approx(0.06) and b["E_bf16"] == pytest.approx(0.09)
-    assert b["E_fp8"] == pytest.approx(0.1 + sb.E_FP8_FORMAT)
+    # N8 = 0.05; the FP8 form sits (0.06, 0.01) from the format oracle, (0.16, 0.11) from the oracle
+    assert b["max_fp8_format_effect"] == pytest.approx(0.1) and b["max_N8"] == pytest.approx(0.05)
+    assert b["E_fp8_form"] == pytest.approx(0.1) and b["E_fp8_format"] == pytest.approx(0.16)
+    assert b["E_fp8"] == pytest.approx(0.26)
 
 
 def test_stored_mixed_oracle_is_self_consistent():
@@ -101,7 +106,8 @@ def test_stored_mixed_oracle_is_self_consistent():
     assert all(np.all(np.isfinite(v)) for v in list(f.values()) + list(j.values()))
 
 
-@pytest.mark.skipif(not os.path.exists(msg.FILTER_FILE), reason="stored filter oracle values not written yet")
+@pytest.mark.skipif(not all(os.path.exists(f) for f in [msg.FILTER_FILE] + sb.FP8_VARIANT_FILES),
+                    reason="stored filter oracle values not written yet")
 def test_stored_filter_oracle_covers_the_sample_and_its_bounds():
     ref, lengths = sb.load_filter_oracle()
     wl = synth.scale_filter(0)
@@ -109,7 +115,7 @@ def test_stored_filter_oracle_covers_the_sample_and_its_bounds():
     assert sorted(lengths) == s
     for d in s:
         for r in wl.r_grid:
-            for v in msg.VARIANTS:
+            for v in msg.VARIANTS + msg.FP8_VARIANTS:
                 assert np.all(np.isfinite(ref[(d, float(r), v)]))
     b = sb.load_bounds()
     _, again = sb.derive(ref)
