@@ -153,7 +153,7 @@ def main():
     K.kvop_pool_destroy(probe)
     free = torch.cuda.mem_get_info()[0]
     log(f"BF16 cache needs {need / 2**30:.1f} GiB, free {free / 2**30:.1f} GiB")
-    prof8 = None
+    prof8, fp8_dec1 = None, None
     pool = K.kvop_pool_create(mb, K.KVOP_KV_BF16, need + (64 << 20))
     pooled = torch.empty(n, shape.d_model, dtype=torch.float32, device=dev)
     hb, t_build = build(pool, 0, n, pooled)
@@ -199,6 +199,8 @@ def main():
             ms, lg, dec = timed_eval(pool8, r, h8, steps=max(1, args.steps // 2), warmup=args.warmup)
             per_r[str(r)]["bf16_fp8kv_tuples_per_s"] = n / (ms / 1e3)
             per_r[str(r)]["fp8kv_vs_bf16kv_decision_disagreement"] = float(np.mean(dec != bf16_out[r][1]))
+            if r == 1.0:
+                fp8_dec1 = dec
             log(f"FP8 r={r}: {ms:.1f} ms/step")
         K.kvop_profile_start()
         timed_eval(pool8, 1.0, h8, steps=1)
@@ -311,8 +313,10 @@ def main():
         "kv_build_bf16_s": result["kv_build_bf16_s"],
         "cpu_baseline": cpu,
     }
+    final_dec = None
     if fp32 is not None and cascade is not None:
-        cascade["vs_fp32_plain_decision_disagreement"] = float(np.mean(cascade.pop("_final") != fp32["dec"]))
+        final_dec = cascade.pop("_final")
+        cascade["vs_fp32_plain_decision_disagreement"] = float(np.mean(final_dec != fp32["dec"]))
     elif cascade is not None:
         cascade.pop("_final")
     if fp32 is not None:
@@ -323,6 +327,22 @@ def main():
                               "bf16_vs_fp32_decision_disagreement": float(np.mean(d16 != fp32["dec"])),
                               "bf16_vs_fp32_max_abs_logit_diff": float(np.max(np.abs(bf16_out[1.0][0] - fp32["logits"]))),
                               "speedup_bf16_over_fp32": value / fp32["tuples_per_s"]}
+        # decisions against the FP32 path (pinned by the oracle to 1e-4) outside the margin band
+        # of each form's error bound, over all tuples at r = 1; the bounds are the ones the
+        # full-size parity test derives from the oracle alone
+        bounds = load_scale_bounds()
+        if bounds:
+            band = {}
+            for tag, dec, E in (("bf16_bf16kv", d16, bounds.get("E_bf16")),
+                                ("bf16_fp8kv", fp8_dec1, bounds.get("E_fp8")),
+                                ("bf16_proxy_cascade", None if cascade is None else final_dec, bounds.get("E_bf16"))):
+                if dec is None or E is None:
+                    continue
+                out = np.abs(lo32) >= 2 * (E + 1e-4)
+                band[tag] = {"E": E, "in_band_fraction": float(1 - out.mean()),
+                             "disagreement_outside_band": float(np.mean((dec != fp32["dec"]) & out)),
+                             "disagreement_all": float(np.mean(dec != fp32["dec"]))}
+            line["fp32_plain"]["decisions_vs_fp32_outside_band"] = band
     print(json.dumps(line), flush=True)
     if args.export_tuning:
         with open(args.export_tuning, "w") as f:
@@ -993,6 +1013,21 @@ def counted_traffic(tile):
         return float(fields["traffic_bytes_per_launch"]) if same_src and same_tile else None
     except (OSError, KeyError, ValueError):
         return None
+
+
+def load_scale_bounds():
+    """The error bounds of the full-size parity test (tests/golden/scale_bounds.txt, derived
+    there from the oracle alone), or {} when absent."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "scale_bounds.txt")
+    out = {}
+    try:
+        for ln in open(path):
+            f = ln.split()
+            if len(f) == 2 and ln[0].isalpha():
+                out[f[0]] = float(f[1])
+    except (OSError, ValueError):
+        return {}
+    return out
 
 
 def trace_launch_us():
