@@ -1365,6 +1365,16 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
   const int qc = m->qkv_cols();
   const int e = m->esz();
   const int64_t own_ld = 2LL * Hkv * D;
+  // map items by rank (call-wide map index), for the decode steps after the waves
+  const std::vector<int> map_by_rank = map_op >= 0 ? by_op[map_op] : std::vector<int>();
+  // Each operator's items enter the waves longest key list first, so that the long items share
+  // the first waves instead of each stretching the attention launch of its own wave (an
+  // item's outputs keep their rank: the order of appearance in the call)
+  for (int k = 0; k < n_ops; k++) {
+    const int nl = ops[k].op.kind == KVOP_JOIN ? 2 : 1;
+    auto keys = [&](int it) { return idx_off[item_list[it] + nl] - idx_off[item_list[it]]; };
+    std::stable_sort(by_op[k].begin(), by_op[k].end(), [&](int a, int b) { return keys(a) > keys(b); });
+  }
   // waves with a fixed per-operator composition: c_k items of operator k per wave
   int64_t total_rows = 0;
   for (int k = 0; k < n_ops; k++) total_rows += (int64_t)by_op[k].size() * ops[k].op.suffix_len;
@@ -1623,7 +1633,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
     for (int g = 0; g < nm_all; g++) ident[g] = g;
     for (int t = 1; t < n_gen; t++)
       for (int g = 0; g < nm_all; g++) {
-        const int it = by_op[map_op][g];
+        const int it = map_by_rank[g];
         const DocSlot* A = docA[it];
         pdec.push_back(A->L + Sm + t - 1);
         ddst.push_back(g * rpi + Sm + t - 1);
