@@ -258,6 +258,18 @@ kvop_status kvop_cascade_eval(kvop_pool* pool, const kvop_op* op, const kvop_sta
                               const kvop_handle* handles_host, int32_t n_items, void* stream, float* logits_out_dev,
                               int8_t* decision_out_dev, int8_t* stage_out_dev, int32_t* processed_host);
 
+/* Parity debugging: the residual stream of the suffix rows after decoder layer `layer`
+ * (0 .. n_layers - 1) of a filter or join evaluation (Section 5, "Online: Query Execution":
+ * the operator query's forward pass over the cached keys/values), for comparison with a
+ * reference layer by layer.  Arguments as kvop_op_eval (map items: EINVAL); output FP32
+ * [n_items, suffix_len, d_model] on the device, caller-owned.  At the last layer only each
+ * item's last suffix row is carried past the attention (the row the head reads); the
+ * item's other rows hold their input to that layer.  Validation, errors and stream
+ * behaviour as kvop_op_eval; no logits or decisions are written. */
+kvop_status kvop_debug_stage(kvop_pool* pool, const kvop_op* op, float r, const int32_t* idx_dev,
+                             const int64_t* idx_offsets_host, const kvop_handle* handles_host, int32_t n_items,
+                             int32_t layer, void* stream, float* hidden_out_dev);
+
 /* ---- batching form -----------------------------------------------------------
  * Mixed operators in one pass (the batched execution of Section 5, "Execution-time
  * Batching", with variable-length work lists instead of padding): the items of

@@ -868,10 +868,12 @@ kvop_status kvop_ea_select(kvop_pool* p, const float* scores, const int64_t* off
 }
 
 // ------------------------------------------------------------------ op_eval
+// dbg_layer >= 0 (with dbg_out): stop every wave after that layer and copy its residual
+// stream (all suffix rows of the wave's items, FP32) to dbg_out instead of evaluating the head
 static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
                                 const kvop_handle* hs, int32_t n_items, const int32_t* select, int32_t n_select,
                                 void* stream, float* logits, int8_t* decision, int32_t* tokens_out,
-                                bool validate_only = false) {
+                                bool validate_only = false, int dbg_layer = -1, float* dbg_out = nullptr) {
   if (!p || !op || n_items < 0 || n_select < 0) return fail(KVOP_EINVAL, "bad arguments");
   if (n_items == 0 || (select && n_select == 0)) return KVOP_OK;
   kvop_model* m = p->m;
@@ -882,7 +884,9 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
   if (!(r > 0.f && r <= 1.f)) return fail(KVOP_EINVAL, "retention must be in (0, 1]");
   const int S = op->suffix_len;
   if (S < 1 || !op->suffix_host) return fail(KVOP_EINVAL, "empty suffix");
-  if (!idx || !idx_off || !hs || !logits) return fail(KVOP_EINVAL, "null buffer");
+  if (!idx || !idx_off || !hs || (!logits && dbg_layer < 0)) return fail(KVOP_EINVAL, "null buffer");
+  if (dbg_layer >= 0 && (kind == KVOP_MAP || select || !dbg_out || dbg_layer >= m->cfg.n_layers))
+    return fail(KVOP_EINVAL, "stage readout: filter or join items, a layer below n_layers and an output buffer");
   for (int j = 0; j < S; j++)
     if (op->suffix_host[j] < 0 || op->suffix_host[j] >= c.vocab) return fail(KVOP_EINVAL, "suffix id out of range");
   int n_gen = 1;
@@ -1110,7 +1114,13 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
                             (const int32_t*)(md + o_od), (int)rows, ownbuf + (size_t)l * B * rows_per_item * own_ld * e,
                             own_ld, st));
       }
+      if (l == dbg_layer) {
+        HIPTRY(hipMemcpyAsync(dbg_out + (int64_t)w0 * S * d, bufs.x, (size_t)rows * d * 4, hipMemcpyDeviceToDevice,
+                              st));
+        break;
+      }
     }
+    if (dbg_layer >= 0) continue;
     const float* xlast = bufs.x + (int64_t)(S - 1) * d;
     if (kind != KVOP_MAP) {
       ProfScope ps(PC_HEAD, st);
@@ -1216,6 +1226,13 @@ kvop_status kvop_op_eval(kvop_pool* p, const kvop_op* op, float r, const int32_t
                          const kvop_handle* hs, int32_t n_items, void* stream, float* logits, int8_t* decision,
                          int32_t* tokens_out) {
   return op_eval_impl(p, op, r, idx, idx_off, hs, n_items, nullptr, 0, stream, logits, decision, tokens_out);
+}
+
+kvop_status kvop_debug_stage(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx, const int64_t* idx_off,
+                             const kvop_handle* hs, int32_t n_items, int32_t layer, void* stream, float* hidden_out) {
+  if (layer < 0) return fail(KVOP_EINVAL, "stage readout: layer must be >= 0");
+  return op_eval_impl(p, op, r, idx, idx_off, hs, n_items, nullptr, 0, stream, nullptr, nullptr, nullptr, false, layer,
+                      hidden_out);
 }
 
 kvop_status kvop_op_eval_select(kvop_pool* p, const kvop_op* op, float r, const int32_t* idx,

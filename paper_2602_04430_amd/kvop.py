@@ -88,6 +88,7 @@ _SIGS = {
     "kvop_proxy_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
     "kvop_proxy_grads": (C.c_int, [_P, _P, _P, _P, C.c_int32, _P, _P, _P]),
     "kvop_proxy_infer": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
+    "kvop_debug_stage": (C.c_int, [_P, _P, C.c_float, _P, _P, _P, C.c_int32, C.c_int32, _P, _P]),
     "kvop_proxy_infer_noalloc": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, _P, _P]),
     "kvop_proxy_params": (C.c_int, [_P, _P, _P]),
     "kvop_set_wave_rows": (C.c_int, [C.c_int64]),
@@ -248,6 +249,16 @@ def kvop_op_eval(pool, op: kvop_op, r: float, idx_dev, idx_offsets: Sequence[int
     n_items = len(h) // (2 if op.kind == KVOP_JOIN else 1)
     _check(lib().kvop_op_eval(pool, C.byref(op), float(r), _dptr(idx_dev), po, hp, n_items, _stream(stream),
                               _dptr(logits_dev), _dptr(decision_dev), _dptr(tokens_dev)))
+
+
+def kvop_debug_stage(pool, op: kvop_op, r: float, idx_dev, idx_offsets: Sequence[int], handles, layer: int,
+                     hidden_dev, stream=None) -> None:
+    """Residual stream of the suffix rows after `layer`: FP32 [n_items, S, d_model] into hidden_dev."""
+    offs, po = _host(idx_offsets, np.int64)
+    h, hp = _host(handles, np.uint64)
+    n_items = len(h) // (2 if op.kind == KVOP_JOIN else 1)
+    _check(lib().kvop_debug_stage(pool, C.byref(op), float(r), _dptr(idx_dev), po, hp, n_items, int(layer),
+                                  _stream(stream), _dptr(hidden_dev)))
 
 
 def kvop_gemm_num_tiles(dtype: int) -> int:

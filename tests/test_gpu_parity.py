@@ -244,6 +244,64 @@ def test_calls_on_two_streams_match_one_stream(device):
     np.testing.assert_array_equal(got[1], ref[1])
 
 
+@pytest.mark.parametrize("kind", ["filter", "join"])
+def test_stage_readout_matches_oracle_layer_by_layer(device, kind):
+    """kvop_debug_stage: the suffix rows' residual stream after every layer of a 3-layer model
+    equals the oracle's, layer by layer (at the last layer, the last row that feeds the head)."""
+    shape = synth.ModelShape(n_layers=3, d_model=256, n_heads=4, n_kv_heads=2, head_dim=64, d_ffn=512, vocab=512)
+    w = synth.make_weights(shape, 14, gain_jitter=0.1)
+    docs = synth.make_docs_uniform(6, 5, 70, shape.vocab, seed=14)
+    suffix = synth.suffix_tokens(7, shape.vocab, seed=14)
+    S = len(suffix)
+    eng = Engine(shape, w, "f32", "f32")
+    handles = eng.build(docs)
+    r = 0.5
+    idx1, offs1 = synth.retained_lists(docs.lengths, r, seed=14)
+    lists = [idx1[offs1[i]:offs1[i + 1]] for i in range(6)]
+    items = [(i,) for i in range(6)] if kind == "filter" else [(0, 3), (5, 1), (2, 2)]
+    sel = [d for it in items for d in it]
+    idx = np.concatenate([lists[d] for d in sel])
+    offs = np.concatenate([[0], np.cumsum([len(lists[d]) for d in sel])])
+    op = K.make_op(K.KVOP_FILTER if kind == "filter" else K.KVOP_JOIN, suffix, synth.YES_ID, synth.NO_ID)
+    m = om.Model(shape, w)
+    caches = [om.kv_build(m, docs.doc(i)) for i in range(6)]
+    # the oracle's suffix pass, layer by layer
+    ref = []
+    for it in items:
+        if kind == "filter":
+            a = it[0]
+            ctxK = [caches[a].K[l][:, lists[a]] for l in range(shape.n_layers)]
+            ctxV = [caches[a].V[l][:, lists[a]] for l in range(shape.n_layers)]
+            n_ctx, pos0 = len(lists[a]), caches[a].length
+        else:
+            a, b = it
+            ctxK, ctxV, n_ctx = om.join_context(m, caches[a], lists[a], caches[b], lists[b])
+            pos0 = caches[a].length + caches[b].length
+        x = m.w["embed"][suffix]
+        vis = np.concatenate([np.ones((S, n_ctx), bool), np.tril(np.ones((S, S), bool))], axis=1)
+        per = []
+        for l in range(shape.n_layers):
+            x, _, _ = m.layer(l, x, pos0 + np.arange(S), ctxK[l], ctxV[l], vis)
+            per.append(x)
+        ref.append(per)
+    for layer in range(shape.n_layers):
+        out = torch.full((len(items), S, shape.d_model), np.nan, dtype=torch.float32, device=device)
+        say("stage readout", kind, "layer", layer)
+        K.kvop_debug_stage(eng.pool, op, r, torch.from_numpy(idx).cuda(), offs, np.array([handles[d] for d in sel]),
+                           layer, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        rows = slice(0, S) if layer + 1 < shape.n_layers else slice(S - 1, S)
+        err = max(float(np.max(np.abs(got[i, rows] - ref[i][layer][rows]))) for i in range(len(items)))
+        say(f"stage readout {kind} layer {layer}: max-abs difference from the oracle {err:.3g}")
+        assert err <= 1e-4, (layer, err)
+    bad = torch.zeros(1, S, shape.d_model, device=device)
+    with pytest.raises(K.KvopError):
+        K.kvop_debug_stage(eng.pool, op, r, torch.from_numpy(idx).cuda(), offs, np.array([handles[d] for d in sel]),
+                           shape.n_layers, bad)
+    eng.close()
+
+
 # ----------------------------------------------------------------------------- map and join
 
 @pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
