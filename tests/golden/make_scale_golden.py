@@ -6,6 +6,7 @@ vocab 32000, normal(0, 0.02) weights, seed 0).  Nothing here calls the GPU libra
   python -m tests.golden.make_scale_golden filter   # scale_filter_oracle.txt, scale_ea_scores.txt
   python -m tests.golden.make_scale_golden fp8w     # scale_filter_oracle_fp8w.txt
   python -m tests.golden.make_scale_golden bf16fp8  # scale_filter_oracle_bf16fp8.txt
+    (fp8w- / bf16fp8-: the same in reverse document order, to share the work with a second run)
   python -m tests.golden.make_scale_golden mixed    # mixed_sample_oracle.txt
 
 filter: 64 documents of the 4096-document filter workload (lognormal lengths, median 512, in
@@ -138,8 +139,11 @@ def make_filter():
     print("wrote", FILTER_FILE, EA_FILE, flush=True)
 
 
-def make_filter_variant(var):
-    """One extra oracle of the 64 sampled filter documents (fp8w or bf16fp8)."""
+def make_filter_variant(var, reverse=False):
+    """One extra oracle of the 64 sampled filter documents (fp8w or bf16fp8).  Two runs may
+    share the work, one forward and one in reverse order (`<var>-`): each skips documents
+    already present in either's partial file, and the run that finds every document done
+    writes the merged file."""
     shape = synth.SCALE
     wl = synth.scale_filter(0)
     docs = wl.docs
@@ -149,15 +153,19 @@ def make_filter_variant(var):
     m = om.Model(shape, wb, act=codecs.bf16_round if var == "bf16fp8" else None)
     lists = {r: synth.retained_lists(docs.lengths, r, seed=0) for r in wl.r_grid}
     path = variant_file(var)
-    part = path + ".partial"
-    done = _done_keys(part, 4)
-    with open(part, "a") as fh:
-        if not done:
-            fh.write("# written by tests/golden/make_scale_golden.py (FP64 oracle only); "
-                     "columns: document L r variant logit_yes logit_no\n")
-        for i in filter_sample(docs.lengths):
+    parts = [path + ".partial", path + ".rev.partial"]
+    mine = parts[1] if reverse else parts[0]
+
+    def done_all():
+        keys = set()
+        for p in parts:
+            keys |= _done_keys(p, 4)
+        return keys
+    sample = filter_sample(docs.lengths)
+    with open(mine, "a") as fh:
+        for i in (reversed(sample) if reverse else sample):
             L = int(docs.lengths[i])
-            if all((str(i), str(L), str(r), var) in done for r in wl.r_grid):
+            if all((str(i), str(L), str(r), var) in done_all() for r in wl.r_grid):
                 continue
             t0 = time.time()
             c = om.kv_build(m, docs.doc(i), store=codecs.fp8_cache_roundtrip)
@@ -167,8 +175,23 @@ def make_filter_variant(var):
                 fh.write(f"{i} {L} {r} {var} {res.logits[0]:.17g} {res.logits[1]:.17g}\n")
             fh.flush()
             print(f"filter document {i} L {L} {var}: {time.time() - t0:.1f} s", flush=True)
-    os.replace(part, path)
-    print("wrote", path, flush=True)
+    keys = done_all()
+    if all((str(i), str(int(docs.lengths[i])), str(r), var) in keys for i in sample for r in wl.r_grid):
+        lines = {}
+        for p in parts:
+            if os.path.exists(p):
+                for line in open(p):
+                    if line.strip() and not line.startswith("#"):
+                        lines[tuple(line.split()[:4])] = line
+        with open(path, "w") as out:
+            out.write("# written by tests/golden/make_scale_golden.py (FP64 oracle only); "
+                      "columns: document L r variant logit_yes logit_no\n")
+            for key in sorted(lines, key=lambda k: (int(k[0]), -float(k[2]))):
+                out.write(lines[key])
+        for p in parts:
+            if os.path.exists(p):
+                os.remove(p)
+        print("wrote", path, flush=True)
 
 
 def make_mixed():
@@ -230,8 +253,8 @@ def make_mixed():
 def main():
     what = sys.argv[1:] or ["filter", "fp8w", "bf16fp8", "mixed"]
     for w in what:
-        if w in FP8_VARIANTS:
-            make_filter_variant(w)
+        if w.rstrip("-") in FP8_VARIANTS:
+            make_filter_variant(w.rstrip("-"), reverse=w.endswith("-"))
         else:
             {"filter": make_filter, "mixed": make_mixed}[w]()
     return 0
