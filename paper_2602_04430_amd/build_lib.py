@@ -16,8 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libkvop.so")
-SOURCES = ["gemm.hip", "attention.hip", "attention_dma.hip", "elementwise.hip", "compress.hip", "proxy.hip", "api.cpp",
-           "proxy_api.cpp", "planner.cpp"]
+SOURCES = ["gemm.hip", "attention.hip", "attention_dma.hip", "attention_decode.hip", "elementwise.hip", "compress.hip",
+           "proxy.hip", "api.cpp", "proxy_api.cpp", "planner.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -1036,6 +1036,8 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
         for (const AttnWork& w : dwork) kmax = std::max(kmax, w.n_a);
         for (AttnWork& w : dwork) w.pad_a = kmax;
       }
+      // longest key lists first, so that no long item starts last (items are independent)
+      std::stable_sort(dwork.begin(), dwork.end(), [](const AttnWork& a, const AttnWork& b) { return a.n_a > b.n_a; });
       own_src.resize(rows);
       own_dst.resize(rows);
       for (int b = 0; b < B; b++)
@@ -1145,9 +1147,9 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
         ddst[b] = b * rows_per_item + S + t - 1;
       }
       std::vector<AttnWork> dw = dwork;
-      for (int b = 0; b < B; b++) {
-        dw[b].q_pos0 = pdec[b];
-        dw[b].n_own = S + t;
+      for (AttnWork& x : dw) {
+        x.q_pos0 = pdec[x.q_row0];
+        x.n_own = S + t;
       }
       if (m->stage.reserve(mir.size) != hipSuccess) return fail(KVOP_EDEVICE, "metadata staging");
       memcpy(m->stage.p + o_sp, pdec.data(), B * 4);
@@ -1165,6 +1167,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
       dp.attn.n_work = B;
       dp.attn.idx = idx;
       dp.attn.Pmax = 1;
+      dp.attn.decode = 1;
       dp.own_from_qkv = false;
       dp.own_stride = own_ld;
       dp.own_kcol = 0;
@@ -1669,6 +1672,10 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
         wk.own_pos0 = A->L;
         dwork.push_back(wk);
       }
+    // each step's items longest key list first, so that no long item starts last
+    for (int t = 1; t < n_gen; t++)
+      std::stable_sort(dwork.begin() + (size_t)(t - 1) * nm_all, dwork.begin() + (size_t)t * nm_all,
+                       [](const AttnWork& a, const AttnWork& b) { return a.n_a > b.n_a; });
     Mirror mir;
     const size_t o_id = mir.add(ident.size() * 4), o_pd = mir.add(pdec.size() * 4), o_dd = mir.add(ddst.size() * 4),
                  o_dw = mir.add(dwork.size() * sizeof(AttnWork));
@@ -1718,6 +1725,7 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
         a.Hkv = Hkv;
         a.G = G;
         a.Pmax = 1;
+        a.decode = 1;
         a.scale_log2 = (float)(1.4426950408889634 / std::sqrt((double)D));
         a.counter = persistent ? counter : nullptr;
         a.persistent_wgs = 2 * m->n_cu;

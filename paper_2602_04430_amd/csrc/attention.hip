@@ -480,7 +480,10 @@ bool attention_is_dma(int cdt, int kvdt, int D) {
 
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st) {
   if (a.n_work <= 0) return hipSuccess;
-  if (attention_is_dma(cdt, kvdt, D)) return attention_dma(kvdt, D, g_attn_impl, a, st);
+  if (attention_is_dma(cdt, kvdt, D)) {
+    if (a.decode && a.Pmax == 1 && attention_decode_ok(kvdt, D, a.G)) return attention_decode(kvdt, D, a, st);
+    return attention_dma(kvdt, D, g_attn_impl, a, st);
+  }
   if (a.counter && a.persistent_wgs < 1) return hipErrorInvalidValue;
   if (a.G * a.Pmax > 64 || a.G < 1 || a.Pmax < 1) return hipErrorInvalidValue;
   if (cdt == DT_F32) {

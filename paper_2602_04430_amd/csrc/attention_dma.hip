@@ -73,15 +73,6 @@ template <int N> __device__ inline void vm_wait() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-__device__ inline u32x4 fp8x8_to_bf16x8(uint32_t lo, uint32_t hi) {
-  u32x4 r;
-  r[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, false));
-  r[1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, true));
-  r[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, false));
-  r[3] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, true));
-  return r;
-}
-
 // ds_read_b64_tr_b16 as inline assembly.  The builtin form makes the compiler wait for every
 // direct-to-LDS load in flight (vmcnt(0)) before it, since it cannot tell which LDS bytes
 // the read touches.  The assembly form is followed by an explicit lgkmcnt(0) wait; the

@@ -53,6 +53,17 @@ __device__ inline uint32_t e4m3_to_bf16(uint32_t c) {
   return __builtin_bit_cast(uint32_t, e4m3_to_f32(c)) >> 16;
 }
 
+// eight E4M3 codes (two dwords, code 0 in the low byte of lo) -> eight bfloat16 values,
+// by the hardware conversion (exact: every E4M3 value is a bfloat16 value)
+__device__ inline u32x4 fp8x8_to_bf16x8(uint32_t lo, uint32_t hi) {
+  u32x4 r;
+  r[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, false));
+  r[1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 1.0f, true));
+  r[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, false));
+  r[3] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 1.0f, true));
+  return r;
+}
+
 // float -> E4M3 (fn) code, round to nearest even, saturating to +-448.
 __device__ inline uint32_t f32_to_e4m3(float x) {
   uint32_t u = __builtin_bit_cast(uint32_t, x);

@@ -73,9 +73,15 @@ struct AttnArgs {
   int persistent_wgs;  // persistent launch: number of workgroups (register-staged kernel)
   int n_cu;            // persistent launch: compute units; the direct-load kernels launch as
                        // many workgroups as fit on them at once
+  int decode;          // 1: a decoding step (one query position per item, no document B); the
+                       // streaming decode kernel serves it where it supports the shape
 };
 // cdt: compute/query dtype (f32 or bf16); kvdt: cache dtype (f32 with f32; bf16/fp8 with bf16)
 hipError_t attention(int cdt, int kvdt, int D, const AttnArgs& a, hipStream_t st);
+// Decoding step (Pmax = 1, no document B), BF16 compute: keys and values streamed from HBM
+// into registers, G query heads of one kv head per workgroup (G in {1, 2, 4}, D in {64, 128})
+bool attention_decode_ok(int kvdt, int D, int G);
+hipError_t attention_decode(int kvdt, int D, const AttnArgs& a, hipStream_t st);
 // BF16 compute with a BF16 or FP8 cache, D in {64, 128}: tiles fetched by direct global->LDS
 // loads.  variant: 0 = 64-key tiles / 2 stages, 1 = 64 / 3, 2 = 32 / 3.
 hipError_t attention_dma(int kvdt, int D, int variant, const AttnArgs& a, hipStream_t st);
