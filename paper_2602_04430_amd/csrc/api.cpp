@@ -303,10 +303,20 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   const int rows = lp.rows;
   const int dt = m->dt;
   { ProfScope ps(PC_RMSNORM, st); HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, rows, d, c.rms_eps, b.h, d, st)); }
+  // BF16 suffix rows: the rotation of queries and keys is fused into the projection's epilogue
+  // (prefill keeps it separate: expected-attention scoring reads the unrotated queries, and
+  // the keys are rotated by the cache writer)
+  const bool fuse_rope = dt == DT_BF16 && n_kvblocks == 0 && !lp.ea_row_off && gemm_rope_supported(D);
   {
     ProfScope ps(PC_GEMM_QKV, st);
     GemmShape s{rows, qc, d, d, d, qc};
-    HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.qkv, s, st));
+    if (fuse_rope) {
+      const RopeEpi re{lp.pos, m->cos_tab, m->sin_tab, D, (H + Hkv) * D, H * D, lp.alt_shift ? b.qalt : nullptr,
+                       lp.alt_shift};
+      HIPTRY(gemm(dt, dt, EPI_ROPE, gemm_pick_tile(dt, EPI_ROPE, s), b.h, W.wqkv, b.qkv, s, st, &re));
+    } else {
+      HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.qkv, s, st));
+    }
   }
   if (lp.ea_row_off) {  // before the rotation: the statistics are of the pre-rotation queries
     ProfScope ps(PC_EA, st);
@@ -319,7 +329,7 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, 0, D, lp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
     HIPTRY(rope_write_kv(dt, kvdt, b.qkv, qc, kvblocks, n_kvblocks, H, Hkv, D, l, c.n_layers, m->cos_tab, m->sin_tab,
                          pool, st));
-  } else {
+  } else if (!fuse_rope) {
     ProfScope ps(PC_ROPE_KV, st);
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, Hkv, D, lp.pos, m->cos_tab, m->sin_tab, lp.alt_shift ? b.qalt : nullptr,
                    lp.alt_shift, st));
@@ -1182,9 +1192,15 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
         HIPTRY(rmsnorm_rows(m->dt, bufs.x, d, W.attn_norm, B, d, c.rms_eps, bufs.h, d, st));
         {
           GemmShape s{B, qc, d, d, d, qc};
-          HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, s), bufs.h, W.wqkv, bufs.qkv, s, st));
+          if (m->dt == DT_BF16 && gemm_rope_supported(D)) {
+            const RopeEpi re{dp.pos, m->cos_tab, m->sin_tab, D, (H + Hkv) * D, H * D, nullptr, nullptr};
+            HIPTRY(gemm(m->dt, m->dt, EPI_ROPE, gemm_pick_tile(m->dt, EPI_ROPE, s), bufs.h, W.wqkv, bufs.qkv, s, st,
+                        &re));
+          } else {
+            HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, s), bufs.h, W.wqkv, bufs.qkv, s, st));
+            HIPTRY(rope_qk(m->dt, bufs.qkv, qc, B, H, Hkv, D, dp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
+          }
         }
-        HIPTRY(rope_qk(m->dt, bufs.qkv, qc, B, H, Hkv, D, dp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
         HIPTRY(copy_kv_rows(m->dt, bufs.qkv, qc, H * D, 2 * Hkv * D, (const int32_t*)(md + o_dsrc),
                             (const int32_t*)(md + o_sd), B, own_l, own_ld, st));
         AttnArgs a = dp.attn;
@@ -1703,9 +1719,14 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
         HIPTRY(rmsnorm_rows(m->dt, db.x, d, Wl.attn_norm, nm_all, d, c.rms_eps, db.h, d, st));
         {
           GemmShape g{nm_all, qc, d, d, d, qc};
-          HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, g), db.h, Wl.wqkv, db.qkv, g, st));
+          if (m->dt == DT_BF16 && gemm_rope_supported(D)) {
+            const RopeEpi re{pd, m->cos_tab, m->sin_tab, D, (H + Hkv) * D, H * D, nullptr, nullptr};
+            HIPTRY(gemm(m->dt, m->dt, EPI_ROPE, gemm_pick_tile(m->dt, EPI_ROPE, g), db.h, Wl.wqkv, db.qkv, g, st, &re));
+          } else {
+            HIPTRY(gemm(m->dt, m->dt, EPI_STORE, gemm_pick_tile(m->dt, EPI_STORE, g), db.h, Wl.wqkv, db.qkv, g, st));
+            HIPTRY(rope_qk(m->dt, db.qkv, qc, nm_all, H, Hkv, D, pd, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
+          }
         }
-        HIPTRY(rope_qk(m->dt, db.qkv, qc, nm_all, H, Hkv, D, pd, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
         HIPTRY(copy_kv_rows(m->dt, db.qkv, qc, H * D, 2 * Hkv * D, id, dd, nm_all, own_l, own_ld, st));
         AttnArgs a{};
         a.work = dw;

@@ -87,6 +87,14 @@ __device__ inline uint32_t f32_to_e4m3(float x) {
   return code | sign;
 }
 
+// Rotary embedding of one pair (x1 at dimension i, x2 at i + D/2) by the angle with cosine c
+// and sine s.  The roundings are spelled out (one product rounded, then a fused multiply-add)
+// so that every kernel that rotates gives the same bits.
+__device__ inline void rope_pair(float x1, float x2, float c, float s, float& y1, float& y2) {
+  y1 = __builtin_fmaf(x1, c, -(x2 * s));
+  y2 = __builtin_fmaf(x2, c, x1 * s);
+}
+
 // Reinterpret a 32-bit lane value as float.  Takes the value by copy: a bit_cast applied
 // directly to an ext-vector element subscript reads element 0 of the vector.
 __device__ inline float as_f32(uint32_t v) { return __builtin_bit_cast(float, v); }

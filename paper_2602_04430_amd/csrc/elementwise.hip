@@ -159,19 +159,13 @@ __global__ __launch_bounds__(256) void rope_kernel(T* __restrict__ qkv, int64_t 
     Vec8<float>::load(cos_t + (int64_t)p2 * half + i, c2);
     Vec8<float>::load(sin_t + (int64_t)p2 * half + i, s2);
 #pragma unroll
-    for (int e = 0; e < 8; e++) {
-      y1[e] = x1[e] * c2[e] - x2[e] * s2[e];
-      y2[e] = x2[e] * c2[e] + x1[e] * s2[e];
-    }
+    for (int e = 0; e < 8; e++) rope_pair(x1[e], x2[e], c2[e], s2[e], y1[e], y2[e]);
     T* va = q_alt + (int64_t)row * ld + head * D;
     Vec8<T>::store(va + i, y1);
     Vec8<T>::store(va + i + half, y2);
   }
 #pragma unroll
-  for (int e = 0; e < 8; e++) {
-    y1[e] = x1[e] * c[e] - x2[e] * s[e];
-    y2[e] = x2[e] * c[e] + x1[e] * s[e];
-  }
+  for (int e = 0; e < 8; e++) rope_pair(x1[e], x2[e], c[e], s[e], y1[e], y2[e]);
   Vec8<T>::store(v + i, y1);
   Vec8<T>::store(v + i + half, y2);
 }
@@ -217,8 +211,7 @@ __global__ __launch_bounds__(256) void write_kv_kernel(const T* __restrict__ qkv
       float x1 = to_f32(row[kcol + i]), x2 = to_f32(row[kcol + i + half]);
       int p = b.p0 + r;
       float c = cos_t[(int64_t)p * half + i], s = sin_t[(int64_t)p * half + i];
-      k1 = x1 * c - x2 * s;
-      k2 = x2 * c + x1 * s;
+      rope_pair(x1, x2, c, s, k1, k2);
       v1 = to_f32(row[vcol + i]);
       v2 = to_f32(row[vcol + i + half]);
     }

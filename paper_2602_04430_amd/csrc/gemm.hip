@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(SCH == 1 && NW == 4 && WM * WN <= 128 * 64 ? 2 : 1)))
 void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
-                                                      int64_t ldb, int64_t ldc, int tiles_m) {
+                                                      int64_t ldb, int64_t ldc, int tiles_m, RopeEpi rp) {
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   constexpr int LDK = BK + (SWZ == 0 ? VEC : 0);  // LDS row pitch (elements)
   constexpr int CPR = BK / VEC;             // chunks per tile row
@@ -310,6 +310,75 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
   }
   if constexpr (NS != 0) __syncthreads();  // every wavefront is done with the slabs (LDS reused below)
 
+  if constexpr (EPI == EPI_ROPE) {
+    // ---- rotary epilogue: the tile's products, rounded to BF16, staged row-major in LDS
+    // (pitch BN + 8), then each thread takes 8-pair groups (dimensions i .. i+7 and
+    // i + D/2 .. i + D/2 + 7 of one head of one row) and rotates them at the row's position
+    // (heads in [0, rot_cols)); the rotation reads the rounded values, as a separate pass
+    // over the stored products would.  Rows are written with 16-byte stores.
+    static_assert(sizeof(T) == 2 && sizeof(TO) == 2, "rotary epilogue: BF16");
+    if constexpr (NS == 0) __syncthreads();
+    constexpr int TP = BN + 8;
+    bf16_t* Tt = reinterpret_cast<bf16_t*>(smem_raw);
+#pragma unroll
+    for (int i = 0; i < MI; i++)
+#pragma unroll
+      for (int j = 0; j < NI; j++)
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+          Tt[(wm * WM + 16 * i + 4 * (lane >> 4) + r) * TP + wn * WN + 16 * j + (lane & 15)] = f2bf(acc[i][j][r]);
+    __syncthreads();
+    const int D = rp.D, half = D >> 1, gph = half >> 3;     // 8-pair groups per head
+    const int upr = (BN / D) * gph;                           // groups per tile row
+    bf16_t* C = reinterpret_cast<bf16_t*>(Cv);
+    bf16_t* Qa = reinterpret_cast<bf16_t*>(rp.q_alt);
+    for (int u = tid; u < BM * upr; u += NT) {
+      const int row = u / upr, w = u - row * upr;
+      const int hh = w / gph, i = (w - hh * gph) * 8;
+      const int gm = m0 + row, col = n0 + hh * D + i;
+      if (gm >= M || col >= N) continue;                    // N is a multiple of D
+      const u32x4 r1 = *reinterpret_cast<const u32x4*>(Tt + row * TP + hh * D + i);
+      const u32x4 r2 = *reinterpret_cast<const u32x4*>(Tt + row * TP + hh * D + i + half);
+      bf16_t* c1 = C + (int64_t)gm * ldc + col;
+      if (col >= rp.rot_cols) {
+        *reinterpret_cast<u32x4*>(c1) = r1;
+        *reinterpret_cast<u32x4*>(c1 + half) = r2;
+        continue;
+      }
+      float x1[8], x2[8];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        x1[2 * q] = __builtin_bit_cast(float, r1[q] << 16);
+        x1[2 * q + 1] = __builtin_bit_cast(float, r1[q] & 0xffff0000u);
+        x2[2 * q] = __builtin_bit_cast(float, r2[q] << 16);
+        x2[2 * q + 1] = __builtin_bit_cast(float, r2[q] & 0xffff0000u);
+      }
+      auto rotate_store = [&](int p, bf16_t* dst) {
+        const f32x4* cp = reinterpret_cast<const f32x4*>(rp.cos_t + (int64_t)p * half + i);
+        const f32x4* sp = reinterpret_cast<const f32x4*>(rp.sin_t + (int64_t)p * half + i);
+        const f32x4 ca = cp[0], cb = cp[1], sa = sp[0], sb = sp[1];
+        float y1[8], y2[8];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          rope_pair(x1[e], x2[e], ca[e], sa[e], y1[e], y2[e]);
+          rope_pair(x1[4 + e], x2[4 + e], cb[e], sb[e], y1[4 + e], y2[4 + e]);
+        }
+        u32x4 o1, o2;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          o1[q] = pack_bf16x2(y1[2 * q], y1[2 * q + 1]);
+          o2[q] = pack_bf16x2(y2[2 * q], y2[2 * q + 1]);
+        }
+        *reinterpret_cast<u32x4*>(dst) = o1;
+        *reinterpret_cast<u32x4*>(dst + half) = o2;
+      };
+      const int p = rp.pos[gm];
+      if (Qa && col < rp.q_cols && rp.shift[gm] >= 0) rotate_store(p - rp.shift[gm], Qa + (int64_t)gm * ldc + col);
+      rotate_store(p, c1);
+    }
+    return;
+  }
+
   // ---- epilogue.  Lane holds C[row0 + 4*(lane/16) + r][col0 + 16*j + lane%16].  Output
   // columns of one 16-row slab are first formed in registers (SwiGLU pairs gate block j with
   // up block j+1), staged row-major through this wavefront's slice of LDS (free after the
@@ -423,15 +492,18 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
   int vec = dt == DT_F32 ? 4 : 8;
   if (s.K % vec || s.lda % vec || s.ldb % vec) return false;
   if (epi == EPI_SWIGLU && (s.N % 32 || (c.WN % 32))) return false;
+  if (epi == EPI_ROPE && (dt != DT_BF16 || c.BN % 128)) return false;   // whole heads of D <= 128 per tile
   if (c.NS && s.K % c.BK) return false;   // direct-load tiles read whole slabs only
   return true;
 }
 
 template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0,
           int SCH = 0>
-static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
+static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st,
+                           const RopeEpi& rp) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
   size_t lds = (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
+  if (EPI == EPI_ROPE) lds = std::max(lds, (size_t)BM * (BN + 8) * 2);   // the staged BF16 tile
   auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, SCH>;
   static bool attr_set = false;
   if (!attr_set) {
@@ -440,62 +512,75 @@ static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShap
     attr_set = true;
   }
   hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(64 * NW), lds, st, (const T*)A, (const T*)B, C, s.M, s.N, s.K,
-                     s.lda, s.ldb, s.ldc, tiles_m);
+                     s.lda, s.ldb, s.ldc, tiles_m, rp);
   return hipGetLastError();
 }
 
 template <typename T, typename TO, int EPI>
-static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st) {
+static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st,
+                             const RopeEpi& rp) {
   if constexpr (sizeof(T) == 4) {
     switch (tile) {
-      case 0: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64, 0>(A, B, C, s, st);
-      case 1: return launch_t<T, TO, EPI, 64, 128, 32, 32, 64, 0>(A, B, C, s, st);
-      case 2: return launch_t<T, TO, EPI, 128, 64, 32, 64, 32, 0>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64, 1>(A, B, C, s, st);
+      case 0: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64, 0>(A, B, C, s, st, rp);
+      case 1: return launch_t<T, TO, EPI, 64, 128, 32, 32, 64, 0>(A, B, C, s, st, rp);
+      case 2: return launch_t<T, TO, EPI, 128, 64, 32, 64, 32, 0>(A, B, C, s, st, rp);
+      default: return launch_t<T, TO, EPI, 128, 128, 32, 64, 64, 1>(A, B, C, s, st, rp);
     }
   } else {
     switch (tile) {
-      case 0: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 0>(A, B, C, s, st);
-      case 1: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 0>(A, B, C, s, st);
-      case 2: return launch_t<T, TO, EPI, 128, 256, 64, 64, 128, 0>(A, B, C, s, st);
-      case 3: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64, 0>(A, B, C, s, st);
-      case 4: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 0>(A, B, C, s, st);
-      case 5: return launch_t<T, TO, EPI, 256, 256, 32, 128, 128, 0>(A, B, C, s, st);
-      case 6: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 1>(A, B, C, s, st);
-      case 7: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 2>(A, B, C, s, st);
-      case 8: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 1>(A, B, C, s, st);
-      case 9: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 1>(A, B, C, s, st);
-      case 10: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8>(A, B, C, s, st);
-      case 11: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8>(A, B, C, s, st);
-      case 12: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 2, 8>(A, B, C, s, st);
-      case 13: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 0, 8>(A, B, C, s, st);
-      case 14: return launch_t<T, TO, EPI, 256, 128, 64, 64, 64, 1, 8>(A, B, C, s, st);
-      case 15: return launch_t<T, TO, EPI, 128, 256, 64, 64, 64, 1, 8>(A, B, C, s, st);
-      case 16: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8, 2>(A, B, C, s, st);
-      case 17: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 3>(A, B, C, s, st);
-      case 18: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 4>(A, B, C, s, st);
-      case 19: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2>(A, B, C, s, st);
-      case 20: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st);
-      case 21: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 3, 1>(A, B, C, s, st);
-      case 22: return launch_t<T, TO, EPI, 128, 256, 32, 64, 128, 3, 4, 3, 1>(A, B, C, s, st);
-      default: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st);
+      case 0: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 0>(A, B, C, s, st, rp);
+      case 1: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 0>(A, B, C, s, st, rp);
+      case 2: return launch_t<T, TO, EPI, 128, 256, 64, 64, 128, 0>(A, B, C, s, st, rp);
+      case 3: return launch_t<T, TO, EPI, 64, 128, 64, 32, 64, 0>(A, B, C, s, st, rp);
+      case 4: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 0>(A, B, C, s, st, rp);
+      case 5: return launch_t<T, TO, EPI, 256, 256, 32, 128, 128, 0>(A, B, C, s, st, rp);
+      case 6: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 1>(A, B, C, s, st, rp);
+      case 7: return launch_t<T, TO, EPI, 128, 128, 64, 64, 64, 2>(A, B, C, s, st, rp);
+      case 8: return launch_t<T, TO, EPI, 256, 256, 64, 128, 128, 1>(A, B, C, s, st, rp);
+      case 9: return launch_t<T, TO, EPI, 256, 128, 64, 128, 64, 1>(A, B, C, s, st, rp);
+      case 10: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8>(A, B, C, s, st, rp);
+      case 11: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8>(A, B, C, s, st, rp);
+      case 12: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 2, 8>(A, B, C, s, st, rp);
+      case 13: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 0, 8>(A, B, C, s, st, rp);
+      case 14: return launch_t<T, TO, EPI, 256, 128, 64, 64, 64, 1, 8>(A, B, C, s, st, rp);
+      case 15: return launch_t<T, TO, EPI, 128, 256, 64, 64, 64, 1, 8>(A, B, C, s, st, rp);
+      case 16: return launch_t<T, TO, EPI, 256, 256, 64, 64, 128, 1, 8, 2>(A, B, C, s, st, rp);
+      case 17: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 3>(A, B, C, s, st, rp);
+      case 18: return launch_t<T, TO, EPI, 256, 256, 32, 64, 128, 3, 8, 4>(A, B, C, s, st, rp);
+      case 19: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2>(A, B, C, s, st, rp);
+      case 20: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st, rp);
+      case 21: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 3, 1>(A, B, C, s, st, rp);
+      case 22: return launch_t<T, TO, EPI, 128, 256, 32, 64, 128, 3, 4, 3, 1>(A, B, C, s, st, rp);
+      default: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st, rp);
     }
   }
 }
 
+bool gemm_rope_supported(int D) { return D >= 16 && D % 16 == 0 && 128 % D == 0; }
+
 hipError_t gemm(int dt, int out_dt, int epi, int tile, const void* A, const void* B, void* C, const GemmShape& s,
-                hipStream_t st) {
+                hipStream_t st, const RopeEpi* rope) {
   if (s.M <= 0 || s.N <= 0) return hipSuccess;
   if (!gemm_tile_ok(dt, tile, s, epi)) return hipErrorInvalidValue;
-  if (dt == DT_F32) {
-    if (epi == EPI_ADD) return launch_cfg<float, float, EPI_ADD>(tile, A, B, C, s, st);
-    if (epi == EPI_SWIGLU) return launch_cfg<float, float, EPI_SWIGLU>(tile, A, B, C, s, st);
-    return launch_cfg<float, float, EPI_STORE>(tile, A, B, C, s, st);
+  const RopeEpi none{};
+  if (epi == EPI_ROPE) {
+    // whole heads per tile (every BF16 tile is 128 or 256 columns wide: D divides 128), 8-pair
+    // groups (D a multiple of 16) and 16-byte rows
+    if (!rope || dt != DT_BF16 || out_dt != DT_BF16 || !gemm_rope_supported(rope->D) || s.N % rope->D ||
+        s.ldc % 8 || (reinterpret_cast<uintptr_t>(C) & 15) || (rope->q_alt && !rope->shift) || !rope->pos ||
+        (reinterpret_cast<uintptr_t>(rope->q_alt) & 15))
+      return hipErrorInvalidValue;
+    return launch_cfg<bf16_t, bf16_t, EPI_ROPE>(tile, A, B, C, s, st, *rope);
   }
-  if (epi == EPI_ADD) return launch_cfg<bf16_t, float, EPI_ADD>(tile, A, B, C, s, st);
-  if (epi == EPI_SWIGLU) return launch_cfg<bf16_t, bf16_t, EPI_SWIGLU>(tile, A, B, C, s, st);
-  if (out_dt == DT_F32) return launch_cfg<bf16_t, float, EPI_STORE>(tile, A, B, C, s, st);
-  return launch_cfg<bf16_t, bf16_t, EPI_STORE>(tile, A, B, C, s, st);
+  if (dt == DT_F32) {
+    if (epi == EPI_ADD) return launch_cfg<float, float, EPI_ADD>(tile, A, B, C, s, st, none);
+    if (epi == EPI_SWIGLU) return launch_cfg<float, float, EPI_SWIGLU>(tile, A, B, C, s, st, none);
+    return launch_cfg<float, float, EPI_STORE>(tile, A, B, C, s, st, none);
+  }
+  if (epi == EPI_ADD) return launch_cfg<bf16_t, float, EPI_ADD>(tile, A, B, C, s, st, none);
+  if (epi == EPI_SWIGLU) return launch_cfg<bf16_t, bf16_t, EPI_SWIGLU>(tile, A, B, C, s, st, none);
+  if (out_dt == DT_F32) return launch_cfg<bf16_t, float, EPI_STORE>(tile, A, B, C, s, st, none);
+  return launch_cfg<bf16_t, bf16_t, EPI_STORE>(tile, A, B, C, s, st, none);
 }
 
 // ------------------------------------------------------------------ tile choice
@@ -533,6 +618,7 @@ bool gemm_tuned_import_line(int dt, int epi, int N, int K, int mb, const std::st
 }
 
 int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
+  if (epi == EPI_ROPE) epi = EPI_STORE;   // same main loop; the store epilogue's tuning applies
   auto it = tuned().find({dt, epi, s.N, s.K, mbucket(s.M)});
   if (it != tuned().end() && gemm_tile_ok(dt, it->second, s, epi)) return it->second;
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;

@@ -9,7 +9,7 @@
 namespace kvop {
 
 enum Dt { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
-enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_SWIGLU = 2 };
+enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_SWIGLU = 2, EPI_ROPE = 3 };
 
 // ---------------------------------------------------------------- GEMM (C = A B^T)
 // A [M, K] (lda), B [N, K] (ldb), both in `dt` (f32 or bf16); FP32 accumulation.
@@ -17,16 +17,31 @@ enum Epi { EPI_STORE = 0, EPI_ADD = 1, EPI_SWIGLU = 2 };
 //   EPI_ADD   : C (FP32) += A B^T           (residual add)
 //   EPI_SWIGLU: B rows interleaved in blocks of 16 (16 gate rows, then the 16 matching
 //               up rows); C[M, N/2] (ldc) in `out_dt` = silu(gate) * up
+//   EPI_ROPE  : BF16 only: C[M, N] in BF16, then the rotary embedding of the D-wide heads in
+//               columns [0, rot_cols) at each row's position (pairs (i, i + D/2)), applied
+//               to the BF16-rounded products exactly as rope_qk applies it; joins also get
+//               the query columns [0, q_cols) rotated at position - shift[row] into q_alt
+//               (same layout) where shift[row] >= 0
 struct GemmShape {
   int M, N, K;
   int64_t lda, ldb, ldc;
+};
+struct RopeEpi {
+  const int32_t* pos;                  // position of each output row
+  const float* cos_t;                  // [position][D/2]
+  const float* sin_t;
+  int D, rot_cols, q_cols;
+  void* q_alt;                         // may be null
+  const int32_t* shift;
 };
 // Tile configurations (autotuner candidates); see gemm.hip.
 int gemm_num_tiles(int dt);
 const char* gemm_tile_name(int dt, int tile);
 bool gemm_tile_ok(int dt, int tile, const GemmShape& s, int epi);
 hipError_t gemm(int dt, int out_dt, int epi, int tile, const void* A, const void* B, void* C, const GemmShape& s,
-                hipStream_t st);
+                hipStream_t st, const RopeEpi* rope = nullptr);
+// head dims the rotary epilogue serves (whole heads in every BF16 tile, 8-pair groups)
+bool gemm_rope_supported(int D);
 // default tile for a shape (from the tuned table when present)
 int gemm_pick_tile(int dt, int epi, const GemmShape& s);
 void gemm_set_tuned(int dt, int epi, int N, int K, int mbucket, int tile);
