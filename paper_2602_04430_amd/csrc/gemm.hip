@@ -320,25 +320,67 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
     if constexpr (NS == 0) __syncthreads();
     constexpr int TP = BN + 8;
     bf16_t* Tt = reinterpret_cast<bf16_t*>(smem_raw);
+    // Lanes 2c and 2c + 1 hold columns 2c and 2c + 1 of the same four rows: a swap of two
+    // values between them (a DPP move) lets the even lane write rows 0-1 and the odd lane
+    // rows 2-3 of the pair as packed BF16 pairs, one 4-byte store each.
+    const bool odd = lane & 1;
+    const int prow = 4 * (lane >> 4) + (odd ? 2 : 0), pcol = (lane & 15) & ~1;
 #pragma unroll
     for (int i = 0; i < MI; i++)
 #pragma unroll
-      for (int j = 0; j < NI; j++)
-#pragma unroll
-        for (int r = 0; r < 4; r++)
-          Tt[(wm * WM + 16 * i + 4 * (lane >> 4) + r) * TP + wn * WN + 16 * j + (lane & 15)] = f2bf(acc[i][j][r]);
+      for (int j = 0; j < NI; j++) {
+        const f32x4 v = acc[i][j];
+        const float s0 = odd ? v[0] : v[2], s1 = odd ? v[1] : v[3];
+        const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s0), 0xB1,
+                                                                                0xF, 0xF, false));
+        const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, s1), 0xB1,
+                                                                                0xF, 0xF, false));
+        const uint32_t w0 = odd ? pack_bf16x2(r0, v[2]) : pack_bf16x2(v[0], r0);
+        const uint32_t w1 = odd ? pack_bf16x2(r1, v[3]) : pack_bf16x2(v[1], r1);
+        bf16_t* t = Tt + (wm * WM + 16 * i + prow) * TP + wn * WN + 16 * j + pcol;
+        *reinterpret_cast<uint32_t*>(t) = w0;
+        *reinterpret_cast<uint32_t*>(t + TP) = w1;
+      }
     __syncthreads();
     const int D = rp.D, half = D >> 1, gph = half >> 3;     // 8-pair groups per head
     const int upr = (BN / D) * gph;                           // groups per tile row
     bf16_t* C = reinterpret_cast<bf16_t*>(Cv);
     bf16_t* Qa = reinterpret_cast<bf16_t*>(rp.q_alt);
-    for (int u = tid; u < BM * upr; u += NT) {
+    // BM * BN / 16 groups whatever D is: a fixed count per thread, fully unrolled so that the
+    // position and table loads of all of them can be in flight together
+    constexpr int NU = BM * BN / 16 / NT;
+    static_assert(NU * 16 * NT == BM * BN, "rotary groups per thread");
+    // phase 1: which group (row, head, 8 dimensions) each of this thread's NU groups is, and
+    // its row's position; phase 2: the table rows at those positions; phase 3: rotate and
+    // store.  No load sits behind a branch, so the loads of every group are in flight at once.
+    int gm_[NU], col_[NU], off_[NU], p_[NU];
+#pragma unroll
+    for (int k = 0; k < NU; k++) {
+      const int u = tid + NT * k;
       const int row = u / upr, w = u - row * upr;
       const int hh = w / gph, i = (w - hh * gph) * 8;
-      const int gm = m0 + row, col = n0 + hh * D + i;
+      gm_[k] = m0 + row;
+      col_[k] = n0 + hh * D + i;
+      off_[k] = row * TP + hh * D + i;
+      p_[k] = rp.pos[min(gm_[k], M - 1)];
+    }
+    f32x4 ct_[NU][2], st_[NU][2];
+#pragma unroll
+    for (int k = 0; k < NU; k++) {
+      const int i = col_[k] % half;
+      const f32x4* cp = reinterpret_cast<const f32x4*>(rp.cos_t + (int64_t)p_[k] * half + i);
+      const f32x4* sp = reinterpret_cast<const f32x4*>(rp.sin_t + (int64_t)p_[k] * half + i);
+      ct_[k][0] = cp[0];
+      ct_[k][1] = cp[1];
+      st_[k][0] = sp[0];
+      st_[k][1] = sp[1];
+    }
+#pragma unroll
+    for (int k = 0; k < NU; k++) {
+      const int gm = gm_[k], col = col_[k];
       if (gm >= M || col >= N) continue;                    // N is a multiple of D
-      const u32x4 r1 = *reinterpret_cast<const u32x4*>(Tt + row * TP + hh * D + i);
-      const u32x4 r2 = *reinterpret_cast<const u32x4*>(Tt + row * TP + hh * D + i + half);
+      const u32x4 r1 = *reinterpret_cast<const u32x4*>(Tt + off_[k]);
+      const u32x4 r2 = *reinterpret_cast<const u32x4*>(Tt + off_[k] + half);
       bf16_t* c1 = C + (int64_t)gm * ldc + col;
       if (col >= rp.rot_cols) {
         *reinterpret_cast<u32x4*>(c1) = r1;
@@ -353,10 +395,7 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
         x2[2 * q] = __builtin_bit_cast(float, r2[q] << 16);
         x2[2 * q + 1] = __builtin_bit_cast(float, r2[q] & 0xffff0000u);
       }
-      auto rotate_store = [&](int p, bf16_t* dst) {
-        const f32x4* cp = reinterpret_cast<const f32x4*>(rp.cos_t + (int64_t)p * half + i);
-        const f32x4* sp = reinterpret_cast<const f32x4*>(rp.sin_t + (int64_t)p * half + i);
-        const f32x4 ca = cp[0], cb = cp[1], sa = sp[0], sb = sp[1];
+      auto rotate_store = [&](const f32x4& ca, const f32x4& cb, const f32x4& sa, const f32x4& sb, bf16_t* dst) {
         float y1[8], y2[8];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
@@ -372,9 +411,14 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
         *reinterpret_cast<u32x4*>(dst) = o1;
         *reinterpret_cast<u32x4*>(dst + half) = o2;
       };
-      const int p = rp.pos[gm];
-      if (Qa && col < rp.q_cols && rp.shift[gm] >= 0) rotate_store(p - rp.shift[gm], Qa + (int64_t)gm * ldc + col);
-      rotate_store(p, c1);
+      if (Qa && col < rp.q_cols && rp.shift[gm] >= 0) {
+        // joins: the query rotated at position - shift (rare rows; loads taken here)
+        const int p2 = p_[k] - rp.shift[gm], i = col % half;
+        const f32x4* cp = reinterpret_cast<const f32x4*>(rp.cos_t + (int64_t)p2 * half + i);
+        const f32x4* sp = reinterpret_cast<const f32x4*>(rp.sin_t + (int64_t)p2 * half + i);
+        rotate_store(cp[0], cp[1], sp[0], sp[1], Qa + (int64_t)gm * ldc + col);
+      }
+      rotate_store(ct_[k][0], ct_[k][1], st_[k][0], st_[k][1], c1);
     }
     return;
   }
