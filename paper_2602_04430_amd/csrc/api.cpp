@@ -288,6 +288,9 @@ struct LayerPlan {
   int ea_nd = 0, ea_n_items = 0, ea_n_future = 0;
   float* ea_e = nullptr;
   float* ea_acc = nullptr;
+  // > 0: every item's rows are the same shared_rows rows before the rotation (layer 0 of one
+  // operator: the suffix's embeddings), so they are normalised and projected once
+  int shared_rows = 0;
   void select_all() { n_groups = 1; sel[0] = SelGroup{rows, 1, 0}; }
   void select_one(int n, int stride, int off) { n_groups = 1; sel[0] = SelGroup{n, stride, off}; }
 };
@@ -302,15 +305,27 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   const int qc = m->qkv_cols();
   const int rows = lp.rows;
   const int dt = m->dt;
-  { ProfScope ps(PC_RMSNORM, st); HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, rows, d, c.rms_eps, b.h, d, st)); }
   // BF16 suffix rows: the rotation of queries and keys is fused into the projection's epilogue
   // (prefill keeps it separate: expected-attention scoring reads the unrotated queries, and
   // the keys are rotated by the cache writer)
   const bool fuse_rope = dt == DT_BF16 && n_kvblocks == 0 && !lp.ea_row_off && gemm_rope_supported(D);
+  // rows shared by every item: normalise and project them once (into the attention output
+  // buffer, free until the attention runs), then copy them to every item rotated at its
+  // positions; the result equals the per-row path bit for bit
+  const int shared = fuse_rope && lp.shared_rows > 0 && rows % lp.shared_rows == 0 &&
+                             (int64_t)rows * H * D >= (int64_t)lp.shared_rows * qc
+                         ? lp.shared_rows
+                         : 0;
+  {
+    ProfScope ps(PC_RMSNORM, st);
+    HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, shared ? shared : rows, d, c.rms_eps, b.h, d, st));
+  }
   {
     ProfScope ps(PC_GEMM_QKV, st);
-    GemmShape s{rows, qc, d, d, d, qc};
-    if (fuse_rope) {
+    GemmShape s{shared ? shared : rows, qc, d, d, d, qc};
+    if (shared) {
+      HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.attn, s, st));
+    } else if (fuse_rope) {
       const RopeEpi re{lp.pos, m->cos_tab, m->sin_tab, D, (H + Hkv) * D, H * D, lp.alt_shift ? b.qalt : nullptr,
                        lp.alt_shift};
       HIPTRY(gemm(dt, dt, EPI_ROPE, gemm_pick_tile(dt, EPI_ROPE, s), b.h, W.wqkv, b.qkv, s, st, &re));
@@ -329,6 +344,10 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, 0, D, lp.pos, m->cos_tab, m->sin_tab, nullptr, nullptr, st));
     HIPTRY(rope_write_kv(dt, kvdt, b.qkv, qc, kvblocks, n_kvblocks, H, Hkv, D, l, c.n_layers, m->cos_tab, m->sin_tab,
                          pool, st));
+  } else if (shared) {
+    ProfScope ps(PC_ROPE_KV, st);
+    HIPTRY(rope_broadcast(b.attn, shared, b.qkv, qc, rows, qc, (H + Hkv) * D, H * D, D, lp.pos, m->cos_tab, m->sin_tab,
+                          lp.alt_shift ? b.qalt : nullptr, lp.alt_shift, st));
   } else if (!fuse_rope) {
     ProfScope ps(PC_ROPE_KV, st);
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, Hkv, D, lp.pos, m->cos_tab, m->sin_tab, lp.alt_shift ? b.qalt : nullptr,
@@ -1117,6 +1136,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     lp.own_from_qkv = true;
     for (int l = 0; l < c.n_layers; l++) {
       const bool last = l + 1 == c.n_layers;
+      lp.shared_rows = l == 0 && B >= 2 ? S : 0;   // layer 0: every item's rows are the suffix's embeddings
       if (last) lp.select_one(B, S, S - 1);  // only the last suffix row of every item feeds the head
       else lp.select_all();
       kvop_status s = run_layer(m, l, bufs, lp, p->base, p->kvdt, nullptr, 0, st);

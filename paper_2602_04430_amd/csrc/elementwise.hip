@@ -187,6 +187,66 @@ hipError_t rope_qk(int dt, void* qkv, int64_t ld, int n_rows, int H, int Hkv, in
   return hipGetLastError();
 }
 
+// Rows of a batch that repeat every src_rows rows before the rotation (every item's rows are
+// the same suffix at layer 0): each row is copied from its source row r mod src_rows, the
+// query and key heads (columns below rot_cols) rotated at the row's own position with the
+// arithmetic of the projection's rotary epilogue, so the rows equal what that epilogue writes
+// bit for bit; joins also get the queries rotated at position - shift into q_alt.
+__global__ __launch_bounds__(256) void rope_broadcast_kernel(const bf16_t* __restrict__ src, int src_rows,
+                                                             bf16_t* __restrict__ dst, int64_t ld, int n_rows,
+                                                             int n_cols, int rot_cols, int q_cols, int D,
+                                                             const int32_t* __restrict__ pos,
+                                                             const float* __restrict__ cos_t,
+                                                             const float* __restrict__ sin_t, bf16_t* __restrict__ q_alt,
+                                                             const int32_t* __restrict__ shift) {
+  const int half = D / 2, gph = half / 8;
+  const int per_row = (n_cols / D) * gph;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (int64_t)per_row * n_rows) return;
+  const int row = (int)(gid / per_row), rem = (int)(gid - (int64_t)row * per_row);
+  const int hh = rem / gph, i = (rem - hh * gph) * 8, col = hh * D + i;
+  const bf16_t* sp = src + (int64_t)(row % src_rows) * ld + col;
+  const u32x4 r1 = *reinterpret_cast<const u32x4*>(sp), r2 = *reinterpret_cast<const u32x4*>(sp + half);
+  bf16_t* o = dst + (int64_t)row * ld + col;
+  if (col >= rot_cols) {
+    *reinterpret_cast<u32x4*>(o) = r1;
+    *reinterpret_cast<u32x4*>(o + half) = r2;
+    return;
+  }
+  float x1[8], x2[8];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    x1[2 * q] = bf2f((bf16_t)(r1[q] & 0xffffu));
+    x1[2 * q + 1] = bf2f((bf16_t)(r1[q] >> 16));
+    x2[2 * q] = bf2f((bf16_t)(r2[q] & 0xffffu));
+    x2[2 * q + 1] = bf2f((bf16_t)(r2[q] >> 16));
+  }
+  auto rotate_store = [&](int p, bf16_t* d) {
+    float c[8], s[8], y1[8], y2[8];
+    Vec8<float>::load(cos_t + (int64_t)p * half + i, c);
+    Vec8<float>::load(sin_t + (int64_t)p * half + i, s);
+#pragma unroll
+    for (int e = 0; e < 8; e++) rope_pair(x1[e], x2[e], c[e], s[e], y1[e], y2[e]);
+    Vec8<bf16_t>::store(d, y1);
+    Vec8<bf16_t>::store(d + half, y2);
+  };
+  const int p = pos[row];
+  if (q_alt && col < q_cols && shift[row] >= 0) rotate_store(p - shift[row], q_alt + (int64_t)row * ld + col);
+  rotate_store(p, o);
+}
+
+hipError_t rope_broadcast(const void* src, int src_rows, void* dst, int64_t ld, int n_rows, int n_cols, int rot_cols,
+                          int q_cols, int D, const int32_t* pos, const float* cos_tab, const float* sin_tab, void* q_alt,
+                          const int32_t* shift, hipStream_t st) {
+  if (n_rows <= 0) return hipSuccess;
+  if (src_rows < 1 || D % 16 || n_cols % D || ld % 8 || (q_alt && !shift)) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)n_rows * (n_cols / D) * (D / 16);
+  hipLaunchKernelGGL(rope_broadcast_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     (const bf16_t*)src, src_rows, (bf16_t*)dst, ld, n_rows, n_cols, rot_cols, q_cols, D, pos, cos_tab,
+                     sin_tab, (bf16_t*)q_alt, shift);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- cache writer (prefill)
 // One workgroup per (16-row block of a document, kv head): rotate k of the block's rows
 // at their positions, then store k and v into the document's region.  FP8 caches get one

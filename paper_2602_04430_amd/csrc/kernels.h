@@ -140,6 +140,13 @@ hipError_t rmsnorm_rows(int dt, const float* x, int64_t ldx, const float* g, int
                         int64_t ldy, hipStream_t st);
 // rotary embedding in place on q heads and k heads of a qkv buffer (dt), row positions
 // pos[row]; when q_alt != null also writes q rotated at pos[row] - alt_shift[row] into q_alt
+// BF16 rows r < n_rows of dst [.][ld] from src row r % src_rows (same layout): columns below
+// rot_cols rotated at pos[r] as the projection's rotary epilogue rotates them, the rest
+// copied; joins: query columns (below q_cols) also rotated at pos[r] - shift[r] into q_alt
+// where shift[r] >= 0
+hipError_t rope_broadcast(const void* src, int src_rows, void* dst, int64_t ld, int n_rows, int n_cols, int rot_cols,
+                          int q_cols, int D, const int32_t* pos, const float* cos_tab, const float* sin_tab, void* q_alt,
+                          const int32_t* shift, hipStream_t st);
 hipError_t rope_qk(int dt, void* qkv, int64_t ld, int n_rows, int H, int Hkv, int D, const int32_t* pos,
                    const float* cos_tab, const float* sin_tab, void* q_alt, const int32_t* alt_shift,
                    hipStream_t st);
