@@ -291,6 +291,9 @@ struct LayerPlan {
   // > 0: every item's rows are the same shared_rows rows before the rotation (layer 0 of one
   // operator: the suffix's embeddings), so they are normalised and projected once
   int shared_rows = 0;
+  // > 0: only the last of every q_last rows continues (the last layer of one operator), so
+  // queries are projected for those rows only (keys and values for all: that row sees them)
+  int q_last = 0;
   void select_all() { n_groups = 1; sel[0] = SelGroup{rows, 1, 0}; }
   void select_one(int n, int stride, int off) { n_groups = 1; sel[0] = SelGroup{n, stride, off}; }
 };
@@ -316,6 +319,7 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
                              (int64_t)rows * H * D >= (int64_t)lp.shared_rows * qc
                          ? lp.shared_rows
                          : 0;
+  const int qlast = fuse_rope && !shared && lp.q_last > 0 && rows % lp.q_last == 0 ? lp.q_last : 0;
   {
     ProfScope ps(PC_RMSNORM, st);
     HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, shared ? shared : rows, d, c.rms_eps, b.h, d, st));
@@ -325,6 +329,21 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
     GemmShape s{shared ? shared : rows, qc, d, d, d, qc};
     if (shared) {
       HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.attn, s, st));
+    } else if (qlast) {
+      const int e = m->esz(), nq = rows / qlast;
+      // keys and values of every row (output columns H D .. qc; keys rotated)
+      GemmShape kv{rows, 2 * Hkv * D, d, d, d, qc};
+      const RopeEpi rk{lp.pos, m->cos_tab, m->sin_tab, D, Hkv * D, 0, nullptr, nullptr, 1};
+      HIPTRY(gemm(dt, dt, EPI_ROPE, gemm_pick_tile(dt, EPI_ROPE, kv), b.h,
+                  (const char*)W.wqkv + (int64_t)H * D * d * e, (char*)b.qkv + (int64_t)H * D * e, kv, st, &rk));
+      // queries of the last row of every item (rows q_last - 1, 2 q_last - 1, ...)
+      GemmShape qs{nq, H * D, d, (int64_t)qlast * d, d, (int64_t)qlast * qc};
+      const int64_t r0 = qlast - 1;
+      const RopeEpi rq{lp.pos + r0, m->cos_tab, m->sin_tab, D, H * D, H * D,
+                       lp.alt_shift ? (char*)b.qalt + r0 * qc * e : nullptr, lp.alt_shift ? lp.alt_shift + r0 : nullptr,
+                       qlast};
+      HIPTRY(gemm(dt, dt, EPI_ROPE, gemm_pick_tile(dt, EPI_ROPE, qs), (const char*)b.h + r0 * d * e, W.wqkv,
+                  (char*)b.qkv + r0 * qc * e, qs, st, &rq));
     } else if (fuse_rope) {
       const RopeEpi re{lp.pos, m->cos_tab, m->sin_tab, D, (H + Hkv) * D, H * D, lp.alt_shift ? b.qalt : nullptr,
                        lp.alt_shift};
@@ -994,8 +1013,9 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     const int64_t rows = (int64_t)B * S;
     // per-row positions and (joins) rotation shifts; per-item work items
     std::vector<int32_t> pos(rows), shift(join ? rows : 0);
-    std::vector<AttnWork> work;
+    std::vector<AttnWork> work, work_last;
     work.reserve((size_t)B * wq);
+    work_last.reserve((size_t)B);
     std::vector<int32_t> pos_dec(kind == KVOP_MAP ? B : 0);
     for (int b = 0; b < B; b++) {
       int it = w0 + b;
@@ -1030,15 +1050,26 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
         w.n_own = std::min(S, q0 + Pmax_s);
         w.own_pos0 = pos0;
         work.push_back(w);
+        if (q0 + Pmax_s >= S) {
+          // the last layer: the item's last row only, against all its own rows
+          w.q_row0 = b * S + S - 1;
+          w.q_pos0 = pos0 + S - 1;
+          w.n_q = 1;
+          w.n_own = S;
+          work_last.push_back(w);
+        }
       }
       if (kind == KVOP_MAP) pos_dec[b] = pos0 + S;
     }
     std::stable_sort(work.begin(), work.end(),
                      [](const AttnWork& a, const AttnWork& b) { return a.n_a + a.n_b > b.n_a + b.n_b; });
+    std::stable_sort(work_last.begin(), work_last.end(),
+                     [](const AttnWork& a, const AttnWork& b) { return a.n_a + a.n_b > b.n_a + b.n_b; });
     if (padded) {
       // every item of the wave iterates over the wave's largest key count (padding of A)
       const int kmax = work.empty() ? 0 : work.front().n_a + work.front().n_b;
       for (AttnWork& w : work) w.pad_a = kmax - w.n_b;
+      for (AttnWork& w : work_last) w.pad_a = kmax - w.n_b;
     }
     // map decode: work items with one query position against (retained rows + own rows)
     std::vector<AttnWork> dwork;
@@ -1080,8 +1111,9 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     Mirror mir;
     size_t o_out = mir.add(out_rows.size() * 4);
     size_t o_pos = mir.add(pos.size() * 4), o_shift = mir.add(shift.size() * 4),
-           o_work = mir.add(work.size() * sizeof(AttnWork)), o_suf = mir.add(S * 4),
-           o_dwork = mir.add(dwork.size() * sizeof(AttnWork)), o_os = mir.add(own_src.size() * 4),
+           o_work = mir.add(work.size() * sizeof(AttnWork)), o_wlast = mir.add(work_last.size() * sizeof(AttnWork)),
+           o_suf = mir.add(S * 4), o_dwork = mir.add(dwork.size() * sizeof(AttnWork)),
+           o_os = mir.add(own_src.size() * 4),
            o_od = mir.add(own_dst.size() * 4), o_pdec = mir.add(pos_dec.size() * 4),
            o_ddst = mir.add(pos_dec.size() * 4), o_dsrc = mir.add(pos_dec.size() * 4),
            o_ntok = mir.add(pos_dec.size() * 4);
@@ -1096,6 +1128,7 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     memcpy(hp + o_pos, pos.data(), pos.size() * 4);
     if (join) memcpy(hp + o_shift, shift.data(), shift.size() * 4);
     memcpy(hp + o_work, work.data(), work.size() * sizeof(AttnWork));
+    memcpy(hp + o_wlast, work_last.data(), work_last.size() * sizeof(AttnWork));
     memcpy(hp + o_suf, suffix.data(), S * 4);
     if (kind == KVOP_MAP) {
       memcpy(hp + o_dwork, dwork.data(), dwork.size() * sizeof(AttnWork));
@@ -1139,6 +1172,11 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
       lp.shared_rows = l == 0 && B >= 2 ? S : 0;   // layer 0: every item's rows are the suffix's embeddings
       if (last) lp.select_one(B, S, S - 1);  // only the last suffix row of every item feeds the head
       else lp.select_all();
+      // the last layer: queries and attention for each item's last row only
+      lp.q_last = last && S > 1 ? S : 0;
+      lp.attn.work = (const AttnWork*)(md + (lp.q_last ? o_wlast : o_work));
+      lp.attn.n_work = (int)(lp.q_last ? work_last.size() : work.size());
+      lp.attn.Pmax = lp.q_last ? 1 : Pmax_s;
       kvop_status s = run_layer(m, l, bufs, lp, p->base, p->kvdt, nullptr, 0, st);
       if (s != KVOP_OK) return s;
       if (kind == KVOP_MAP) {

@@ -353,6 +353,7 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
     // phase 1: which group (row, head, 8 dimensions) each of this thread's NU groups is, and
     // its row's position; phase 2: the table rows at those positions; phase 3: rotate and
     // store.  No load sits behind a branch, so the loads of every group are in flight at once.
+    const int ps = rp.pos_stride > 0 ? rp.pos_stride : 1;
     int gm_[NU], col_[NU], off_[NU], p_[NU];
 #pragma unroll
     for (int k = 0; k < NU; k++) {
@@ -362,7 +363,7 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
       gm_[k] = m0 + row;
       col_[k] = n0 + hh * D + i;
       off_[k] = row * TP + hh * D + i;
-      p_[k] = rp.pos[min(gm_[k], M - 1)];
+      p_[k] = rp.pos[(int64_t)min(gm_[k], M - 1) * ps];
     }
     f32x4 ct_[NU][2], st_[NU][2];
 #pragma unroll
@@ -411,9 +412,9 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
         *reinterpret_cast<u32x4*>(dst) = o1;
         *reinterpret_cast<u32x4*>(dst + half) = o2;
       };
-      if (Qa && col < rp.q_cols && rp.shift[gm] >= 0) {
+      if (Qa && col < rp.q_cols && rp.shift[(int64_t)gm * ps] >= 0) {
         // joins: the query rotated at position - shift (rare rows; loads taken here)
-        const int p2 = p_[k] - rp.shift[gm], i = col % half;
+        const int p2 = p_[k] - rp.shift[(int64_t)gm * ps], i = col % half;
         const f32x4* cp = reinterpret_cast<const f32x4*>(rp.cos_t + (int64_t)p2 * half + i);
         const f32x4* sp = reinterpret_cast<const f32x4*>(rp.sin_t + (int64_t)p2 * half + i);
         rotate_store(cp[0], cp[1], sp[0], sp[1], Qa + (int64_t)gm * ldc + col);

@@ -33,6 +33,7 @@ struct RopeEpi {
   int D, rot_cols, q_cols;
   void* q_alt;                         // may be null
   const int32_t* shift;
+  int pos_stride;                      // row r's position and shift at index r * pos_stride (0: 1)
 };
 // Tile configurations (autotuner candidates); see gemm.hip.
 int gemm_num_tiles(int dt);
