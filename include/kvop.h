@@ -356,6 +356,18 @@ kvop_status kvop_proxy_params(kvop_proxy* proxy, float* params_out_dev, void* st
  * interleaved gate/up rows of B (C has N/2 columns).  Device pointers; strides in
  * elements.  EINVAL when the tile cannot run the shape (K, lda, ldb must be
  * multiples of 16 bytes / element size). */
+/* The projection with its rotary epilogue (BF16 operands A [M, K], B [N, K], row-major,
+ * K-contiguous; C [M, N] BF16): C = A B^T rounded to BF16, then the heads of width head_dim in
+ * columns [0, rot_cols) rotated pairwise (i, i + head_dim/2) by the angles of row r's
+ * position pos_dev[r] (cos_dev / sin_dev: [position][head_dim/2] FP32 tables), Section 5's
+ * rotary positions of the suffix rows.  fused = 1 runs the epilogue inside the projection
+ * (the form op_eval uses), fused = 0 the plain projection followed by a separate rotation
+ * pass; both must give the same bits.  head_dim must divide 128 and be a multiple of 16;
+ * N and rot_cols multiples of head_dim; EINVAL otherwise or when the tile cannot run the shape.
+ * Device pointers; C is overwritten. */
+kvop_status kvop_debug_gemm_rope(int32_t tile, const void* A, const void* B, void* Cm, int32_t M, int32_t N, int32_t K,
+                                 int32_t head_dim, int32_t rot_cols, const int32_t* pos_dev, const float* cos_dev,
+                                 const float* sin_dev, int32_t fused, void* stream);
 int32_t kvop_gemm_num_tiles(int32_t dtype);
 const char* kvop_gemm_tile_name(int32_t dtype, int32_t tile);
 kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epilogue, int32_t tile, const void* A,

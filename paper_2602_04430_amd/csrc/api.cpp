@@ -2012,6 +2012,29 @@ kvop_status kvop_debug_gemm(int32_t dtype, int32_t out_dtype, int32_t epi, int32
   return KVOP_OK;
 }
 
+kvop_status kvop_debug_gemm_rope(int32_t tile, const void* A, const void* B, void* Cm, int32_t M, int32_t N, int32_t K,
+                                 int32_t head_dim, int32_t rot_cols, const int32_t* pos_dev, const float* cos_dev,
+                                 const float* sin_dev, int32_t fused, void* stream) {
+  if (!A || !B || !Cm || !pos_dev || !cos_dev || !sin_dev || M < 0 || N < 1 || K < 1 || rot_cols < 0 || rot_cols > N ||
+      !gemm_rope_supported(head_dim) || N % head_dim || rot_cols % head_dim)
+    return fail(KVOP_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  GemmShape s{M, N, K, K, K, N};
+  const int epi = fused ? EPI_ROPE : EPI_STORE;
+  if (tile < 0) tile = gemm_pick_tile(DT_BF16, epi, s);
+  if (!gemm_tile_ok(DT_BF16, tile, s, epi)) return fail(KVOP_EINVAL, "tile cannot run this shape");
+  if (fused) {
+    const RopeEpi re{pos_dev, cos_dev, sin_dev, head_dim, rot_cols, 0, nullptr, nullptr, 1};
+    HIPTRY(gemm(DT_BF16, DT_BF16, EPI_ROPE, tile, A, B, Cm, s, st, &re));
+  } else {
+    // the plain product, then the separate pass (each element read and written by one thread)
+    HIPTRY(gemm(DT_BF16, DT_BF16, EPI_STORE, tile, A, B, Cm, s, st));
+    HIPTRY(rope_broadcast(Cm, std::max(M, 1), Cm, N, M, N, rot_cols, 0, head_dim, pos_dev, cos_dev, sin_dev, nullptr,
+                          nullptr, st));
+  }
+  return KVOP_OK;
+}
+
 kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epi, int32_t N, int32_t K, int32_t M, int32_t tile) {
   int dt = dtype == KVOP_F32 ? DT_F32 : DT_BF16;
   if (tile < 0 || tile >= gemm_num_tiles(dt) || M < 1) return fail(KVOP_EINVAL, "bad tile");

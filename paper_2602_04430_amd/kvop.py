@@ -73,6 +73,8 @@ _SIGS = {
     "kvop_op_eval": (C.c_int, [_P, C.POINTER(kvop_op), C.c_float, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
     "kvop_gemm_num_tiles": (C.c_int32, [C.c_int32]),
     "kvop_gemm_tile_name": (C.c_char_p, [C.c_int32, C.c_int32]),
+    "kvop_debug_gemm_rope": (C.c_int, [C.c_int32, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       _P, _P, _P, C.c_int32, _P]),
     "kvop_debug_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P]),
     "kvop_gemm_set_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
@@ -273,6 +275,12 @@ def kvop_debug_gemm(dtype: int, out_dtype: int, epilogue: int, tile: int, A, B, 
                     lda: int, ldb: int, ldc: int, stream=None) -> None:
     _check(lib().kvop_debug_gemm(dtype, out_dtype, epilogue, tile, _dptr(A), _dptr(B), _dptr(Cm), M, N, K, lda, ldb,
                                  ldc, _stream(stream)))
+
+
+def kvop_debug_gemm_rope(tile: int, A, B, Cm, M: int, N: int, K: int, head_dim: int, rot_cols: int, pos, cos_t, sin_t,
+                         fused: bool, stream=None) -> None:
+    _check(lib().kvop_debug_gemm_rope(tile, _dptr(A), _dptr(B), _dptr(Cm), M, N, K, head_dim, rot_cols, _dptr(pos),
+                                      _dptr(cos_t), _dptr(sin_t), int(bool(fused)), _stream(stream)))
 
 
 def kvop_gemm_set_tile(dtype: int, epilogue: int, N: int, K: int, M: int, tile: int) -> None:

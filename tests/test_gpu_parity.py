@@ -64,6 +64,52 @@ def test_gemm_every_tile_matches_float64(device, dtype, epi):
             assert err <= tol, (dtype, epi, M, N, Kd, tile, err, tol)
 
 
+@pytest.mark.parametrize("D", [32, 64, 128])
+def test_rotary_epilogue_every_tile(device, D):
+    """The projection with its rotary epilogue, for every BF16 tile: bit-identical to the plain
+    projection followed by the separate rotation pass, rotated columns within two BF16 units in
+    the last place (plus the FP32 rounding of a cancelling rotation) of a float64 rotation of
+    the tile's own plain products, and the columns
+    past rot_cols equal to those products.  Ragged rows and a column edge inside a tile."""
+    rng = np.random.default_rng(D)
+    M, N, Kd = 300, 640, 256
+    rot = N - 2 * D
+    half = D // 2
+    A = _bf16(torch.from_numpy(rng.standard_normal((M, Kd)).astype(np.float32) * 0.5)).to(device)
+    B = _bf16(torch.from_numpy(rng.standard_normal((N, Kd)).astype(np.float32) * 0.05)).to(device)
+    n_pos = 4096
+    pos = rng.integers(0, n_pos, M).astype(np.int32)
+    inv = 10000.0 ** (-np.arange(half) * 2.0 / D)
+    ang = np.arange(n_pos)[:, None] * inv[None, :]
+    cos_t = torch.from_numpy(np.cos(ang).astype(np.float32)).to(device)
+    sin_t = torch.from_numpy(np.sin(ang).astype(np.float32)).to(device)
+    pos_d = torch.from_numpy(pos).to(device)
+    c64, s64 = np.cos(ang).astype(np.float32).astype(np.float64), np.sin(ang).astype(np.float32).astype(np.float64)
+    checked = 0
+    for tile in range(K.kvop_gemm_num_tiles(K.KVOP_BF16)):
+        outs = []
+        for fused in (True, False):
+            C = torch.full((M, N), float("nan"), dtype=torch.bfloat16, device=device)
+            K.kvop_debug_gemm_rope(tile, A, B, C, M, N, Kd, D, rot, pos_d, cos_t, sin_t, fused)
+            outs.append(C)
+        plain = torch.full((M, N), float("nan"), dtype=torch.bfloat16, device=device)
+        K.kvop_debug_gemm(K.KVOP_BF16, K.KVOP_BF16, 0, tile, A, B, plain, M, N, Kd, Kd, Kd, N)
+        torch.cuda.synchronize()
+        fz, sp, pl = (t.float().cpu().numpy().astype(np.float64) for t in (outs[0], outs[1], plain))
+        assert np.array_equal(fz, sp), (tile, K.kvop_gemm_tile_name(K.KVOP_BF16, tile))
+        np.testing.assert_array_equal(fz[:, rot:], pl[:, rot:])
+        x = pl[:, :rot].reshape(M, rot // D, 2, half)
+        c, s_ = c64[pos][:, None, :], s64[pos][:, None, :]
+        ref = np.stack([x[:, :, 0] * c - x[:, :, 1] * s_, x[:, :, 1] * c + x[:, :, 0] * s_], axis=2).reshape(M, rot)
+        # two BF16 units in the last place, plus the FP32 rounding of the rotation itself where
+        # the result cancels towards zero
+        err = np.abs(fz[:, :rot] - ref)
+        assert np.all(err <= 2.0 ** -6 * np.abs(ref) + 2.0 ** -20 * np.abs(x).max()), (tile, float(err.max()))
+        checked += 1
+    say(f"rotary epilogue, D={D}: {checked} tiles fused == separate pass, within 2 BF16 ulp of float64")
+    assert checked == K.kvop_gemm_num_tiles(K.KVOP_BF16)
+
+
 # ----------------------------------------------------------------------------- kv_build
 
 @pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
