@@ -359,8 +359,10 @@ kvop_status kvop_proxy_params(kvop_proxy* proxy, float* params_out_dev, void* st
 /* The projection with its rotary epilogue (BF16 operands A [M, K], B [N, K], row-major,
  * K-contiguous; C [M, N] BF16): C = A B^T rounded to BF16, then the heads of width head_dim in
  * columns [0, rot_cols) rotated pairwise (i, i + head_dim/2) by the angles of row r's
- * position pos_dev[r] (cos_dev / sin_dev: [position][head_dim/2] FP32 tables), Section 5's
- * rotary positions of the suffix rows.  fused = 1 runs the epilogue inside the projection
+ * position pos_dev[r] (cos_dev / sin_dev: [position][head_dim/2] FP32 tables): the decoder's
+ * rotary embedding, applied to the operator query that Section 5 appends to each cached item,
+ * so a query row j after an item of L cached rows sits at position L + j.  fused = 1 runs the
+ * epilogue inside the projection
  * (the form op_eval uses), fused = 0 the plain projection followed by a separate rotation
  * pass; both must give the same bits.  head_dim must divide 128 and be a multiple of 16;
  * N and rot_cols multiples of head_dim; EINVAL otherwise or when the tile cannot run the shape.
