@@ -499,10 +499,11 @@ __device__ void attn_dma_unit(const AttnArgs& a, int unit, uint8_t* smem) {
 }
 
 // One workgroup per unit.
-// 32-key compute steps keep three workgroups' registers per CU (and their tiles fit LDS);
+// 32-key compute steps keep three workgroups' registers per CU (and their tiles fit LDS), or
+// four with two stages (128 VGPRs: four wavefronts per SIMD; 34 KB of LDS per workgroup);
 // the register budget is capped to match
 template <typename TKV, int D, int KT, int NS, int KC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KC == 32 ? 3 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KC == 32 ? (NS == 2 ? 4 : 3) : 1)))
 void attn_dma_kernel(AttnArgs a) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dma_smem[];
   attn_dma_unit<TKV, D, KT, NS, KC>(a, blockIdx.x, dma_smem);
@@ -559,11 +560,17 @@ static hipError_t launch_dma(const AttnArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// variant: 0 = KT 64 / 2 stages, 1 = KT 64 / 3 stages, 2 = 32-key compute steps / 3 stages
-// with 16 KiB of keys and values per stage: 32-key tiles of a BF16 cache, 64-key tiles of an
-// FP8 cache (its rows are half as long, so the tile moves the same bytes and a workgroup
-// keeps as many bytes in flight), each computed as two 32-key steps.
-// (D = 64 has no 32-key variant: its FP8 tile would be under one chunk load per thread)
+// variant: 0 = KT 64 / 2 stages, 1 = KT 64 / 3 stages, 2 = 32-key compute steps over tiles of
+// 16 KiB of keys and values: 32-key tiles of a BF16 cache, 64-key tiles of an FP8 cache (its
+// rows are half as long, so the tile moves the same bytes), each computed in 32-key steps.
+// The BF16 form runs two stages and four resident workgroups per CU (one tile in flight per
+// workgroup, four per CU): a step's chain of dependent operations is then hidden by four
+// wavefronts per SIMD instead of three, and HBM needs no more bytes in flight per CU than
+// that; its persistent form keeps three stages (at four wavefronts per SIMD it would spill).
+// The FP8 form needs more registers (three workgroups per CU whatever the stages) and keeps
+// three stages.  The stage count changes no arithmetic: all forms of a variant agree bit
+// for bit.  (D = 64 has no 32-key variant: its FP8 tile would be under one chunk load per
+// thread.)
 template <typename TKV, int D>
 static hipError_t launch_dma_variant(int variant, const AttnArgs& a, hipStream_t st) {
   if (variant == 0) return launch_dma<TKV, D, 64, 2>(a, st);
@@ -571,7 +578,8 @@ static hipError_t launch_dma_variant(int variant, const AttnArgs& a, hipStream_t
   else {
     if (variant == 1) return launch_dma<TKV, D, 64, 3>(a, st);
     if constexpr (sizeof(TKV) == 1) return launch_dma<TKV, D, 64, 3, 32>(a, st);
-    else return launch_dma<TKV, D, 32, 3>(a, st);
+    else if (a.counter) return launch_dma<TKV, D, 32, 3>(a, st);
+    else return launch_dma<TKV, D, 32, 2>(a, st);
   }
 }
 
