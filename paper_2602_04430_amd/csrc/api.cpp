@@ -288,9 +288,14 @@ struct LayerPlan {
   int ea_nd = 0, ea_n_items = 0, ea_n_future = 0;
   float* ea_e = nullptr;
   float* ea_acc = nullptr;
-  // > 0: every item's rows are the same shared_rows rows before the rotation (layer 0 of one
-  // operator: the suffix's embeddings), so they are normalised and projected once
-  int shared_rows = 0;
+  // blocks of rows that repeat every `period` rows before the rotation (layer 0: every item of
+  // an operator starts from the embeddings of that operator's suffix), so each block's first
+  // period rows are normalised and projected once; the blocks cover every row
+  struct SharedBlock {
+    int row0, rows, period;
+  };
+  SharedBlock shared[kMaxSelGroups];
+  int n_shared = 0;
   // > 0: only the last of every q_last rows continues (the last layer of one operator), so
   // queries are projected for those rows only (keys and values for all: that row sees them)
   int q_last = 0;
@@ -312,25 +317,50 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
   // (prefill keeps it separate: expected-attention scoring reads the unrotated queries, and
   // the keys are rotated by the cache writer)
   const bool fuse_rope = dt == DT_BF16 && n_kvblocks == 0 && !lp.ea_row_off && gemm_rope_supported(D);
-  // rows shared by every item: normalise and project them once (into the attention output
-  // buffer, free until the attention runs), then copy them to every item rotated at its
+  // rows shared by every item of a block: normalise and project them once (into the attention
+  // output buffer, free until the attention runs), then copy them to every item rotated at its
   // positions; the result equals the per-row path bit for bit
-  const int shared = fuse_rope && lp.shared_rows > 0 && rows % lp.shared_rows == 0 &&
-                             (int64_t)rows * H * D >= (int64_t)lp.shared_rows * qc
-                         ? lp.shared_rows
-                         : 0;
+  const int e = m->esz();
+  bool shared = fuse_rope && lp.n_shared > 0;
+  {
+    int64_t covered = 0, periods = 0;
+    for (int i = 0; i < lp.n_shared; i++) {
+      const LayerPlan::SharedBlock& sb = lp.shared[i];
+      if (sb.period < 1 || sb.rows < 0 || sb.rows % sb.period) shared = false;
+      covered += sb.rows;
+      periods += sb.period;
+    }
+    if (covered != rows || periods * qc > (int64_t)rows * H * D) shared = false;
+  }
   const int qlast = fuse_rope && !shared && lp.q_last > 0 && rows % lp.q_last == 0 ? lp.q_last : 0;
   {
     ProfScope ps(PC_RMSNORM, st);
-    HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, shared ? shared : rows, d, c.rms_eps, b.h, d, st));
+    if (shared) {
+      for (int i = 0; i < lp.n_shared; i++) {
+        const LayerPlan::SharedBlock& sb = lp.shared[i];
+        if (sb.rows == 0) continue;
+        HIPTRY(rmsnorm_rows(dt, b.x + (int64_t)sb.row0 * d, d, W.attn_norm, sb.period, d, c.rms_eps,
+                            (char*)b.h + (int64_t)sb.row0 * d * e, d, st));
+      }
+    } else {
+      HIPTRY(rmsnorm_rows(dt, b.x, d, W.attn_norm, rows, d, c.rms_eps, b.h, d, st));
+    }
   }
   {
     ProfScope ps(PC_GEMM_QKV, st);
-    GemmShape s{shared ? shared : rows, qc, d, d, d, qc};
+    GemmShape s{rows, qc, d, d, d, qc};
     if (shared) {
-      HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, s), b.h, W.wqkv, b.attn, s, st));
+      int64_t off = 0;
+      for (int i = 0; i < lp.n_shared; i++) {
+        const LayerPlan::SharedBlock& sb = lp.shared[i];
+        if (sb.rows == 0) continue;
+        GemmShape sg{sb.period, qc, d, d, d, qc};
+        HIPTRY(gemm(dt, dt, EPI_STORE, gemm_pick_tile(dt, EPI_STORE, sg), (const char*)b.h + (int64_t)sb.row0 * d * e,
+                    W.wqkv, (char*)b.attn + off * qc * e, sg, st));
+        off += sb.period;
+      }
     } else if (qlast) {
-      const int e = m->esz(), nq = rows / qlast;
+      const int nq = rows / qlast;
       // keys and values of every row (output columns H D .. qc; keys rotated)
       GemmShape kv{rows, 2 * Hkv * D, d, d, d, qc};
       const RopeEpi rk{lp.pos, m->cos_tab, m->sin_tab, D, Hkv * D, 0, nullptr, nullptr, 1};
@@ -365,8 +395,17 @@ kvop_status run_layer(kvop_model* m, int l, const LayerBufs& b, LayerPlan& lp, u
                          pool, st));
   } else if (shared) {
     ProfScope ps(PC_ROPE_KV, st);
-    HIPTRY(rope_broadcast(b.attn, shared, b.qkv, qc, rows, qc, (H + Hkv) * D, H * D, D, lp.pos, m->cos_tab, m->sin_tab,
-                          lp.alt_shift ? b.qalt : nullptr, lp.alt_shift, st));
+    int64_t off = 0;
+    for (int i = 0; i < lp.n_shared; i++) {
+      const LayerPlan::SharedBlock& sb = lp.shared[i];
+      if (sb.rows == 0) continue;
+      const int64_t r0 = sb.row0;
+      HIPTRY(rope_broadcast((char*)b.attn + off * qc * e, sb.period, (char*)b.qkv + r0 * qc * e, qc, sb.rows, qc,
+                            (H + Hkv) * D, H * D, D, lp.pos + r0, m->cos_tab, m->sin_tab,
+                            lp.alt_shift ? (char*)b.qalt + r0 * qc * e : nullptr,
+                            lp.alt_shift ? lp.alt_shift + r0 : nullptr, st));
+      off += sb.period;
+    }
   } else if (!fuse_rope) {
     ProfScope ps(PC_ROPE_KV, st);
     HIPTRY(rope_qk(dt, b.qkv, qc, rows, H, Hkv, D, lp.pos, m->cos_tab, m->sin_tab, lp.alt_shift ? b.qalt : nullptr,
@@ -1169,7 +1208,9 @@ static kvop_status op_eval_impl(kvop_pool* p, const kvop_op* op, float r, const 
     lp.own_from_qkv = true;
     for (int l = 0; l < c.n_layers; l++) {
       const bool last = l + 1 == c.n_layers;
-      lp.shared_rows = l == 0 && B >= 2 ? S : 0;   // layer 0: every item's rows are the suffix's embeddings
+      // layer 0: every item's rows are the suffix's embeddings
+      lp.n_shared = l == 0 && B >= 2 ? 1 : 0;
+      lp.shared[0] = LayerPlan::SharedBlock{0, (int)rows, S};
       if (last) lp.select_one(B, S, S - 1);  // only the last suffix row of every item feeds the head
       else lp.select_all();
       // the last layer: queries and attention for each item's last row only
@@ -1633,6 +1674,13 @@ kvop_status kvop_mixed_eval(kvop_pool* p, const kvop_mixed_op* ops, int32_t n_op
       lp.attn.n_cu = m->n_cu;
       lp.own_from_qkv = true;
       for (int l = 0; l < c.n_layers; l++) {
+        // layer 0: the rows of each operator's block repeat that operator's suffix
+        lp.n_shared = 0;
+        if (l == 0 && n_ops <= kMaxSelGroups)
+          for (int k = 0; k < n_ops; k++)
+            if (blk_n[k] > 0)
+              lp.shared[lp.n_shared++] =
+                  LayerPlan::SharedBlock{blk_row[k], blk_n[k] * ops[k].op.suffix_len, ops[k].op.suffix_len};
         // the last layer continues with each operator's last suffix rows only (one strided
         // group per operator); with more operators than groups every row continues
         lp.select_all();
