@@ -413,6 +413,62 @@ def test_join_pairs_match_oracle(device, compute, kv):
     eng.close()
 
 
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16")])
+@pytest.mark.parametrize("S", [1, 2, 33])
+@pytest.mark.parametrize("n_items", [1, 5])
+def test_suffix_length_and_batch_edges(device, compute, kv, S, n_items):
+    """Filter, join and map at the edges of the suffix-row paths: a one-token suffix (layer 0's
+    shared projection with period 1, no last-layer query trimming), a single item (no shared
+    projection), and a suffix longer than one attention work item (33 rows against 32 per
+    unit for two query heads per kv head: the last layer's work list takes the second unit)."""
+    shape = MICRO_GQA
+    w = synth.make_weights(shape, 40 + S, gain_jitter=0.1)
+    docs = synth.make_docs_uniform(2 * n_items, 1, 90, shape.vocab, seed=40 + S)
+    suffix = synth.suffix_tokens(S, shape.vocab, seed=40 + S)
+    eng = Engine(shape, w, compute, kv)
+    handles = eng.build(docs)
+    m = om.Model(shape, w)
+    caches = [om.kv_build(m, docs.doc(i)) for i in range(2 * n_items)]
+    E = BOUND[(compute, kv)]
+    r = 0.5
+    idx1, offs1 = synth.retained_lists(docs.lengths, r, seed=40 + S)
+    lists = [idx1[offs1[i]:offs1[i + 1]] for i in range(2 * n_items)]
+    say("suffix edges", compute, S, n_items)
+    # filter over the first n_items documents
+    sel = list(range(n_items))
+    idx = np.concatenate([lists[i] for i in sel])
+    offs = np.concatenate([[0], np.cumsum([len(lists[i]) for i in sel])])
+    lg, dec = eng.filter(handles[:n_items], idx, offs, suffix, r=r)
+    lo = []
+    for j, i in enumerate(sel):
+        ref = om.filter_eval(m, caches[i], lists[i], suffix, synth.YES_ID, synth.NO_ID)
+        assert np.max(np.abs(lg[j] - ref.logits)) <= E, ("filter", j)
+        lo.append(ref.log_odds)
+    assert decisions_agree_outside_band(lo, dec, E)[0] == 0
+    # join of pairs (i, n_items + i)
+    hs, jidx, joffs = [], [], [0]
+    for i in range(n_items):
+        for x in (i, n_items + i):
+            hs.append(handles[x])
+            jidx.append(lists[x])
+            joffs.append(joffs[-1] + len(lists[x]))
+    lg, dec = eng.filter(np.array(hs, np.uint64), np.concatenate(jidx), np.array(joffs), suffix, r=r,
+                         kind=K.KVOP_JOIN)
+    lo = []
+    for i in range(n_items):
+        ref = om.join_eval(m, caches[i], lists[i], caches[n_items + i], lists[n_items + i], suffix, synth.YES_ID,
+                           synth.NO_ID)
+        assert np.max(np.abs(lg[i] - ref.logits)) <= E, ("join", i)
+        lo.append(ref.log_odds)
+    assert decisions_agree_outside_band(lo, dec, E)[0] == 0
+    # map (three greedy ids)
+    mlg, tk = eng.map(handles[:n_items], idx, offs, suffix, 256, 256, 3, r=r)
+    refs = [om.map_eval(m, caches[i], lists[i], suffix, 256, 256, 3) for i in sel]
+    checked, whole, err, fails = check_map(tk, mlg, refs, E)
+    assert not fails, fails
+    eng.close()
+
+
 # ----------------------------------------------------------------------------- invariances
 
 @pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "fp8")])
