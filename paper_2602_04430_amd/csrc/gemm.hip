@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64 * NW)
 __attribute__((amdgpu_waves_per_eu(SCH == 1 && NW == 4 && WM * WN <= 128 * 64 ? 2 : 1)))
 void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
                                                       void* __restrict__ Cv, int M, int N, int K, int64_t lda,
-                                                      int64_t ldb, int64_t ldc, int tiles_m, RopeEpi rp) {
+                                                      int64_t ldb, int64_t ldc, int tiles_m, int gm, RopeEpi rp) {
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   constexpr int LDK = BK + (SWZ == 0 ? VEC : 0);  // LDS row pitch (elements)
   constexpr int CPR = BK / VEC;             // chunks per tile row
@@ -72,12 +72,14 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
   // Tile order.  The dispatcher hands workgroup b to XCD b % 8; remap so that every XCD
   // owns one contiguous range of logical tiles, then walk that range in groups of GM
   // M-tiles x all N-tiles (M fastest inside a group) so that the A and B tiles of
-  // concurrently resident workgroups are shared in that XCD's L2.
+  // concurrently resident workgroups are shared in that XCD's L2.  GM is a property of the
+  // tile (4 or 8), left to the autotuner: on the 256x256 pipelined tile at M = 131072, 4 is
+  // faster for gate/up, O and down and 8 for QKV.
   const int nblk = gridDim.x, bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3, q = nblk >> 3, rem = nblk & 7;
   const int lt = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + loc;
   const int tiles_n = nblk / tiles_m;
-  constexpr int GM = 8;
+  const int GM = gm;
   const int per_group = GM * tiles_n;
   const int first_m = (lt / per_group) * GM;
   const int gsz = min(tiles_m - first_m, GM);
@@ -524,9 +526,10 @@ static const TileCfg kBf16Tiles[] = {
     {256, 128, 32, 128, 64, 3, 4, 3, "bf16_256x128x32_w128x64_swz3_lds3_pipe"},
     {128, 256, 32, 64, 128, 3, 4, 3, "bf16_128x256x32_w64x128_swz3_lds3_pipe"},
     {256, 128, 32, 128, 64, 3, 4, 2, "bf16_256x128x32_w128x64_swz3_lds2_pipe"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pipe_g4"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 24; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 25; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -545,7 +548,7 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
 template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0,
           int SCH = 0>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st,
-                           const RopeEpi& rp) {
+                           const RopeEpi& rp, int gm = 8) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
   size_t lds = (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
   if (EPI == EPI_ROPE) lds = std::max(lds, (size_t)BM * (BN + 8) * 2);   // the staged BF16 tile
@@ -557,7 +560,7 @@ static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShap
     attr_set = true;
   }
   hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(64 * NW), lds, st, (const T*)A, (const T*)B, C, s.M, s.N, s.K,
-                     s.lda, s.ldb, s.ldc, tiles_m, rp);
+                     s.lda, s.ldb, s.ldc, tiles_m, gm, rp);
   return hipGetLastError();
 }
 
@@ -596,7 +599,8 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 20: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st, rp);
       case 21: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 3, 1>(A, B, C, s, st, rp);
       case 22: return launch_t<T, TO, EPI, 128, 256, 32, 64, 128, 3, 4, 3, 1>(A, B, C, s, st, rp);
-      default: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st, rp);
+      case 23: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st, rp);
+      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st, rp, 4);
     }
   }
 }
@@ -669,7 +673,8 @@ int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
   if (s.M <= 128) return 3;        // 64x128
   if (s.M < 8192) return 7;        // 128x128, 4 wavefronts
-  if (gemm_tile_ok(dt, 20, s, epi)) return 20;  // 256x256, 8 wavefronts of 128x64, direct loads, pipelined
+  if (gemm_tile_ok(dt, 24, s, epi)) return 24;  // 256x256, 8 wavefronts of 128x64, direct loads, pipelined,
+                                                // groups of 4 M-tiles
   return 11;                       // 256x256, 8 wavefronts of 64x128
 }
 
