@@ -2092,6 +2092,12 @@ kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epi, int32_t N, int32_t K,
   return KVOP_OK;
 }
 
+int32_t kvop_gemm_pick_tile(int32_t dtype, int32_t epi, int32_t M, int32_t N, int32_t K) {
+  if ((dtype != KVOP_F32 && dtype != KVOP_BF16) || epi < 0 || epi > 3 || M < 1 || N < 1 || K < 1) return -1;
+  const GemmShape s{M, N, K, K, K, N};
+  return gemm_pick_tile(dtype == KVOP_F32 ? DT_F32 : DT_BF16, epi, s);
+}
+
 kvop_status kvop_debug_read_cache(kvop_pool* p, kvop_handle h, int32_t layer, int32_t kv_head, int32_t kv,
                                   float* out, void* stream) {
   if (!p || !out) return fail(KVOP_EINVAL, "null argument");

@@ -78,6 +78,7 @@ _SIGS = {
     "kvop_debug_gemm": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32,
                                   C.c_int32, C.c_int64, C.c_int64, C.c_int64, _P]),
     "kvop_gemm_set_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "kvop_gemm_pick_tile": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "kvop_debug_read_cache": (C.c_int, [_P, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "kvop_cascade_eval": (C.c_int, [_P, C.POINTER(kvop_op), C.POINTER(kvop_stage), C.c_int32, _P, C.c_int32, _P, _P,
                                     _P, _P, _P]),
@@ -285,6 +286,10 @@ def kvop_debug_gemm_rope(tile: int, A, B, Cm, M: int, N: int, K: int, head_dim: 
 
 def kvop_gemm_set_tile(dtype: int, epilogue: int, N: int, K: int, M: int, tile: int) -> None:
     _check(lib().kvop_gemm_set_tile(dtype, epilogue, N, K, M, tile))
+
+
+def kvop_gemm_pick_tile(dtype: int, epilogue: int, M: int, N: int, K: int) -> int:
+    return int(lib().kvop_gemm_pick_tile(dtype, epilogue, M, N, K))
 
 
 def kvop_debug_read_cache(pool, handle, layer: int, kv_head: int, kv: int, out_dev, stream=None) -> None:
