@@ -404,9 +404,8 @@ kvop_status kvop_tuning_import(const char* text);
 kvop_status kvop_gemm_set_tile(int32_t dtype, int32_t epilogue, int32_t N, int32_t K, int32_t M, int32_t tile);
 /* The tile the library uses for a projection of M x N x K (operands row-major with lda = ldb = K;
  * epilogue 0 store, 1 FP32 add, 2 SwiGLU, 3 rotary, which takes the store tuning): the tuning
- * table's tile for (dtype, epilogue, N, K, floor(log2 M)); else the tile of a tuned neighbouring
- * bucket (M within a factor of two of a tuned size), the nearer one in log2 M; else the built-in
- * default for M.  Host state only, no device needed.  -1 for arguments out of range. */
+ * table's tile for (dtype, epilogue, N, K, floor(log2 M)), else the built-in default for M.
+ * Host state only, no device needed.  -1 for arguments out of range. */
 int32_t kvop_gemm_pick_tile(int32_t dtype, int32_t epilogue, int32_t M, int32_t N, int32_t K);
 /* Attention kernel used for BF16 compute with a BF16 or FP8 cache and head_dim 64 or 128
  * (all other cases use the register-staged kernel): -1 = register-staged key/value tiles;

@@ -12,7 +12,6 @@
 // gate/up column blocks.  The workgroup -> tile order is XCD-aware and grouped (see the
 // kernel body) so that concurrently resident workgroups of one XCD share A and B tiles.
 #include <algorithm>
-#include <cmath>
 #include <map>
 #include <string>
 #include <tuple>
@@ -669,25 +668,8 @@ bool gemm_tuned_import_line(int dt, int epi, int N, int K, int mb, const std::st
 
 int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   if (epi == EPI_ROPE) epi = EPI_STORE;   // same main loop; the store epilogue's tuning applies
-  const int mb = mbucket(s.M);
-  auto it = tuned().find({dt, epi, s.N, s.K, mb});
+  auto it = tuned().find({dt, epi, s.N, s.K, mbucket(s.M)});
   if (it != tuned().end() && gemm_tile_ok(dt, it->second, s, epi)) return it->second;
-  // an untuned row count near a tuned one (a neighbouring bucket: M within a factor of two)
-  // takes that bucket's tile, the nearer of the two on a log scale; e.g. a selection of a few
-  // items less than a tuned batch
-  const double lm = std::log2((double)std::max(s.M, 1));
-  int best = -1;
-  double best_d = 1e30;
-  for (int nb : {mb - 1, mb + 1}) {
-    auto jt = tuned().find({dt, epi, s.N, s.K, nb});
-    if (jt == tuned().end() || !gemm_tile_ok(dt, jt->second, s, epi)) continue;
-    const double dist = std::fabs(lm - (nb + 0.5));
-    if (dist < best_d) {
-      best_d = dist;
-      best = jt->second;
-    }
-  }
-  if (best >= 0) return best;
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
   if (s.M <= 128) return 3;        // 64x128
   if (s.M < 8192) return 7;        // 128x128, 4 wavefronts

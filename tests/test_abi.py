@@ -71,25 +71,26 @@ def test_tuning_table_text_roundtrip():
     assert f"1 2 11264 2048 17 {K.kvop_gemm_tile_name(K.KVOP_BF16, 0)}" in K.kvop_tuning_export()
 
 
-def test_tile_choice_falls_back_to_a_neighbouring_tuned_bucket():
-    """A row count whose bucket is untuned takes the tile of a tuned bucket next to it (the
-    nearer in log2 M), e.g. a selection of a few items less than a tuned batch; farther row
-    counts keep the built-in default."""
+def test_tile_choice_is_the_tuned_bucket_else_the_default():
+    """A projection takes the tuned tile of its own bucket floor(log2 M) only; a row count in
+    an untuned bucket, even next to a tuned one, keeps the built-in default for its M (the
+    tile that suits M rows, since tile counts and rounds change with M)."""
     bf, N, Kd = K.KVOP_BF16, 11264, 4096        # a shape no other test tunes
     default_big = K.kvop_gemm_pick_tile(bf, 2, 131072, N, Kd)
-    t17, t15, t12 = 0, 1, 2
-    assert default_big not in (t17, t15, t12)
+    default_small = K.kvop_gemm_pick_tile(bf, 2, 4062, N, Kd)
+    t17, t12 = 0, 1
+    assert default_big not in (t17, t12) and default_small not in (t17, t12)
     K.kvop_gemm_set_tile(bf, 2, N, Kd, 131072, t17)    # bucket 17
-    K.kvop_gemm_set_tile(bf, 2, N, Kd, 40000, t15)     # bucket 15
     K.kvop_gemm_set_tile(bf, 2, N, Kd, 4096, t12)      # bucket 12
     assert K.kvop_gemm_pick_tile(bf, 2, 131072, N, Kd) == t17
-    assert K.kvop_gemm_pick_tile(bf, 2, 129984, N, Kd) == t17     # bucket 16: 17 is nearer
-    assert K.kvop_gemm_pick_tile(bf, 2, 70000, N, Kd) == t15      # bucket 16: 15 is nearer
-    assert K.kvop_gemm_pick_tile(bf, 2, 300000, N, Kd) == t17     # bucket 18
-    assert K.kvop_gemm_pick_tile(bf, 2, 4062, N, Kd) == t12       # bucket 11
-    assert K.kvop_gemm_pick_tile(bf, 2, 8191, N, Kd) == t12       # bucket 12 itself
-    assert K.kvop_gemm_pick_tile(bf, 2, 1 << 20, N, Kd) == default_big    # bucket 20: no neighbour
-    assert K.kvop_gemm_pick_tile(bf, 0, 129984, N, Kd) == default_big     # another epilogue
+    assert K.kvop_gemm_pick_tile(bf, 2, 262143, N, Kd) == t17     # still bucket 17
+    assert K.kvop_gemm_pick_tile(bf, 2, 8191, N, Kd) == t12       # still bucket 12
+    assert K.kvop_gemm_pick_tile(bf, 2, 129984, N, Kd) == default_big     # bucket 16
+    assert K.kvop_gemm_pick_tile(bf, 2, 4062, N, Kd) == default_small     # bucket 11
+    assert K.kvop_gemm_pick_tile(bf, 0, 131072, N, Kd) == default_big     # another epilogue
+    assert K.kvop_gemm_pick_tile(bf, 3, 131072, N, Kd) == default_big     # rotary: the store tuning
+    K.kvop_gemm_set_tile(bf, 0, N, Kd, 131072, t12)
+    assert K.kvop_gemm_pick_tile(bf, 3, 131072, N, Kd) == t12
     assert K.kvop_gemm_pick_tile(bf, 2, 0, N, Kd) == -1 and K.kvop_gemm_pick_tile(7, 2, 64, N, Kd) == -1
 
 
