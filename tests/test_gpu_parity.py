@@ -413,7 +413,7 @@ def test_join_pairs_match_oracle(device, compute, kv):
     eng.close()
 
 
-@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16")])
+@pytest.mark.parametrize("compute,kv", [("f32", "f32"), ("bf16", "bf16"), ("bf16", "fp8")])
 @pytest.mark.parametrize("S", [1, 2, 33])
 @pytest.mark.parametrize("n_items", [1, 5])
 def test_suffix_length_and_batch_edges(device, compute, kv, S, n_items):
