@@ -35,7 +35,7 @@ namespace kvop {
 // and each slab's direct loads are issued between MFMAs; one workgroup barrier per slab,
 // placed where the last fragments of a slab are already in registers.
 template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW, int NS,
-          int SCH = 0>
+          int SCH = 0, int NSB = 0>
 __global__ __launch_bounds__(64 * NW)
 // pipelined 4-wavefront tiles with up to 128x64 per wavefront: registers for two resident
 // workgroups, whose barriers and epilogues then overlap each other's MFMAs
@@ -66,6 +66,14 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int STAGE = (BM + BN) * LDK;
+  // NSB = 0: NS stages of [A slab | B slab].  NSB > NS (pipelined schedule only): NS A-slab
+  // buffers followed by NSB B-slab buffers, so the B slabs are fetched one slab further ahead
+  // (the 256x256 tile's two stages leave exactly one B slab of LDS free).
+  constexpr int NB = NSB ? NSB : NS;
+  constexpr bool SPLIT = NB != NS;
+  static_assert(!SPLIT || (SCH == 1 && NS == 2 && NB == 3), "split stages: pipelined, 2 A + 3 B");
+  auto a_base = [&](int bf) -> T* { return SPLIT ? smem + bf * BM * LDK : smem + bf * STAGE; };
+  auto b_base = [&](int bf) -> T* { return SPLIT ? smem + NS * BM * LDK + bf * BN * LDK : smem + bf * STAGE + BM * LDK; };
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN_CNT, wn = wave % WN_CNT;
@@ -144,9 +152,8 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
   // direct loads of slab k0 into buffer buf: chunk f = i NT + 64 wave + lane lands at LDS
   // chunk f (row f / CPR, slot f % CPR) and holds logical chunk slot(row, f % CPR) (the
   // XOR swizzle is its own inverse); rows past M / N read the last row (never stored)
-  auto dma = [&](int k0, int bf) {
-    T* As = smem + bf * STAGE;
-    T* Bs = As + BM * LDK;
+  auto dma_a = [&](int k0, int bf) {
+    T* As = a_base(bf);
 #pragma unroll
     for (int i = 0; i < ACH; i++) {
       const int f = tid + i * NT, r = f / CPR, c = slot(r, f % CPR);
@@ -155,6 +162,9 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
       uint8_t* l = reinterpret_cast<uint8_t*>(As + (i * NT + 64 * wave) * VEC);
       __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
     }
+  };
+  auto dma_b = [&](int k0, int bf) {
+    T* Bs = b_base(bf);
 #pragma unroll
     for (int i = 0; i < BCH; i++) {
       const int f = tid + i * NT, r = f / CPR, c = slot(r, f % CPR);
@@ -164,20 +174,27 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
       __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)l, 16, 0, 0);
     }
   };
+  auto dma = [&](int k0, int bf) {
+    dma_a(k0, bf);
+    dma_b(k0, bf);
+  };
   if constexpr (SCH == 1) {
     static_assert(NS >= 2 && sizeof(T) == 2 && (BK == KSUB || BK == 2 * KSUB),
                   "pipelined: direct loads, BF16, one or two MFMA steps per slab");
     constexpr int HS = BK / KSUB;                     // MFMA steps per slab
     constexpr int OPS = ACH + BCH;                    // direct loads per thread per slab
-    constexpr int VMW = (NS - 2) * OPS, VMP = (NS - 1) * OPS;
+    // loads allowed in flight at the first wait (slab 0 landed) and at each slab boundary
+    // (slab kt + 1 landed): split stages issue A0 B0 A1 B1 B2 ahead, then one A and one B slab
+    // per boundary (A kt + 2, B kt + 3), so only the newest B slab may still be in flight
+    constexpr int VMW = SPLIT ? BCH : (NS - 2) * OPS, VMP = SPLIT ? (NS - 1) * OPS + (NB - NS) * BCH : (NS - 1) * OPS;
     static_assert(VMP <= 63, "vmcnt range");
     constexpr int VM_STEADY = (VMW & 15) | ((VMW >> 4) << 14) | (7 << 4) | (15 << 8);
     constexpr int VM_FIRST = (VMP & 15) | ((VMP >> 4) << 14) | (7 << 4) | (15 << 8);
     constexpr int LGKM0 = 0xC07F;
     // fragments of step hs of the slab in buffer bf
-    auto rd = [&](int bf, int hs, u32x4* a_, u32x4* b_) __attribute__((always_inline)) {
-      const T* As = smem + bf * STAGE + (wm * WM) * LDK;
-      const T* Bs = smem + bf * STAGE + BM * LDK + (wn * WN) * LDK;
+    auto rd = [&](int slab, int hs, u32x4* a_, u32x4* b_) __attribute__((always_inline)) {
+      const T* As = a_base(slab % NS) + (wm * WM) * LDK;
+      const T* Bs = b_base(slab % NB) + (wn * WN) * LDK;
 #pragma unroll
       for (int i = 0; i < MI; i++)
         a_[i] = *reinterpret_cast<const u32x4*>(As + (i * 16 + lrow) * LDK + slot(lrow, hs * 4 + lg) * VEC);
@@ -191,6 +208,8 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
     // basic block per step, free for the scheduler to interleave.
 #pragma unroll
     for (int q = 0; q < NS; q++) dma(min(q, nk - 1) * BK, q);
+#pragma unroll
+    for (int q = NS; q < NB; q++) dma_b(min(q, nk - 1) * BK, q);
     __builtin_amdgcn_s_waitcnt(VM_FIRST);             // slab 0 landed (this thread's part)
     __builtin_amdgcn_s_barrier();                     // ... and every thread's
     __builtin_amdgcn_sched_barrier(0);
@@ -199,7 +218,7 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
     // waits for the next slab, passes the barrier and refills the buffer just consumed
     auto step = [&](int kt, auto hs_c, u32x4* ca, u32x4* cb, u32x4* na, u32x4* nb) __attribute__((always_inline)) {
       constexpr int HSV = decltype(hs_c)::value;
-      int nbf = kt % NS, nhs = HSV + 1;
+      int nsl = kt, nhs = HSV + 1;
       __builtin_amdgcn_sched_barrier(0);
       if constexpr (HSV == HS - 1) {
         // slab kt + 1 visible, slab kt's buffer free (all its fragments are in registers)
@@ -208,11 +227,12 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
-        dma(min(kt + NS, nk - 1) * BK, kt % NS);
-        nbf = min(kt + 1, nk - 1) % NS;
+        dma_a(min(kt + NS, nk - 1) * BK, kt % NS);
+        dma_b(min(kt + NB, nk - 1) * BK, kt % NB);
+        nsl = min(kt + 1, nk - 1);
         nhs = 0;
       }
-      rd(nbf, nhs, na, nb);
+      rd(nsl, nhs, na, nb);
 #pragma unroll
       for (int i = 0; i < MI; i++)
 #pragma unroll
@@ -527,9 +547,10 @@ static const TileCfg kBf16Tiles[] = {
     {128, 256, 32, 64, 128, 3, 4, 3, "bf16_128x256x32_w64x128_swz3_lds3_pipe"},
     {256, 128, 32, 128, 64, 3, 4, 2, "bf16_256x128x32_w128x64_swz3_lds2_pipe"},
     {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pipe_g4"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2b3_pipe_g4"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 25; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 26; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -546,13 +567,15 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
 }
 
 template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0,
-          int SCH = 0>
+          int SCH = 0, int NSB = 0>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st,
                            const RopeEpi& rp, int gm = 8) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
-  size_t lds = (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * (BK + (SWZ == 0 ? 16 / sizeof(T) : 0)) * sizeof(T);
+  const size_t ldk = BK + (SWZ == 0 ? 16 / sizeof(T) : 0);
+  size_t lds = NSB ? ((size_t)NS * BM + (size_t)NSB * BN) * ldk * sizeof(T)
+                   : (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * ldk * sizeof(T);
   if (EPI == EPI_ROPE) lds = std::max(lds, (size_t)BM * (BN + 8) * 2);   // the staged BF16 tile
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, SCH>;
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, SCH, NSB>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -600,7 +623,8 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 21: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 3, 1>(A, B, C, s, st, rp);
       case 22: return launch_t<T, TO, EPI, 128, 256, 32, 64, 128, 3, 4, 3, 1>(A, B, C, s, st, rp);
       case 23: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st, rp);
-      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st, rp, 4);
+      case 24: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st, rp, 4);
+      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1, 3>(A, B, C, s, st, rp, 4);
     }
   }
 }
