@@ -35,7 +35,7 @@ namespace kvop {
 // and each slab's direct loads are issued between MFMAs; one workgroup barrier per slab,
 // placed where the last fragments of a slab are already in registers.
 template <typename T, typename TO, int BM, int BN, int BK, int WM, int WN, int EPI, int SWZ, int NW, int NS,
-          int SCH = 0, int NSB = 0>
+          int SCH = 0, int NSB = 0, int NSA = 0>
 __global__ __launch_bounds__(64 * NW)
 // pipelined 4-wavefront tiles with up to 128x64 per wavefront: registers for two resident
 // workgroups, whose barriers and epilogues then overlap each other's MFMAs
@@ -66,14 +66,14 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
   constexpr int STAGE = (BM + BN) * LDK;
-  // NSB = 0: NS stages of [A slab | B slab].  NSB > NS (pipelined schedule only): NS A-slab
-  // buffers followed by NSB B-slab buffers, so the B slabs are fetched one slab further ahead
-  // (the 256x256 tile's two stages leave exactly one B slab of LDS free).
-  constexpr int NB = NSB ? NSB : NS;
-  constexpr bool SPLIT = NB != NS;
-  static_assert(!SPLIT || (SCH == 1 && NS == 2 && NB == 3), "split stages: pipelined, 2 A + 3 B");
+  // NSA = NSB = 0: NS stages of [A slab | B slab].  Split stages (pipelined schedule only):
+  // NA A-slab buffers followed by NB B-slab buffers, one operand fetched one slab further
+  // ahead than the other (the 256x256 tile's two stages leave exactly one slab of LDS free).
+  constexpr int NA = NSA ? NSA : NS, NB = NSB ? NSB : NS;
+  constexpr bool SPLIT = NA != NS || NB != NS;
+  static_assert(!SPLIT || (SCH == 1 && NS == 2 && NA + NB == 5), "split stages: pipelined, 2 + 3");
   auto a_base = [&](int bf) -> T* { return SPLIT ? smem + bf * BM * LDK : smem + bf * STAGE; };
-  auto b_base = [&](int bf) -> T* { return SPLIT ? smem + NS * BM * LDK + bf * BN * LDK : smem + bf * STAGE + BM * LDK; };
+  auto b_base = [&](int bf) -> T* { return SPLIT ? smem + NA * BM * LDK + bf * BN * LDK : smem + bf * STAGE + BM * LDK; };
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN_CNT, wn = wave % WN_CNT;
@@ -184,16 +184,18 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
     constexpr int HS = BK / KSUB;                     // MFMA steps per slab
     constexpr int OPS = ACH + BCH;                    // direct loads per thread per slab
     // loads allowed in flight at the first wait (slab 0 landed) and at each slab boundary
-    // (slab kt + 1 landed): split stages issue A0 B0 A1 B1 B2 ahead, then one A and one B slab
-    // per boundary (A kt + 2, B kt + 3), so only the newest B slab may still be in flight
-    constexpr int VMW = SPLIT ? BCH : (NS - 2) * OPS, VMP = SPLIT ? (NS - 1) * OPS + (NB - NS) * BCH : (NS - 1) * OPS;
+    // (slab kt + 1 landed).  Split stages issue A0 B0 A1 B1 and the deeper operand's slab 2
+    // ahead, then per boundary the shallower operand's slab kt + 2 followed by the deeper one's
+    // slab kt + 3, so only that newest slab may still be in flight at a boundary
+    constexpr int XOPS = NB > NA ? BCH : ACH;        // loads of the deeper operand's slab
+    constexpr int VMW = SPLIT ? XOPS : (NS - 2) * OPS, VMP = SPLIT ? (NS - 1) * OPS + XOPS : (NS - 1) * OPS;
     static_assert(VMP <= 63, "vmcnt range");
     constexpr int VM_STEADY = (VMW & 15) | ((VMW >> 4) << 14) | (7 << 4) | (15 << 8);
     constexpr int VM_FIRST = (VMP & 15) | ((VMP >> 4) << 14) | (7 << 4) | (15 << 8);
     constexpr int LGKM0 = 0xC07F;
     // fragments of step hs of the slab in buffer bf
     auto rd = [&](int slab, int hs, u32x4* a_, u32x4* b_) __attribute__((always_inline)) {
-      const T* As = a_base(slab % NS) + (wm * WM) * LDK;
+      const T* As = a_base(slab % NA) + (wm * WM) * LDK;
       const T* Bs = b_base(slab % NB) + (wn * WN) * LDK;
 #pragma unroll
       for (int i = 0; i < MI; i++)
@@ -210,6 +212,8 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
     for (int q = 0; q < NS; q++) dma(min(q, nk - 1) * BK, q);
 #pragma unroll
     for (int q = NS; q < NB; q++) dma_b(min(q, nk - 1) * BK, q);
+#pragma unroll
+    for (int q = NS; q < NA; q++) dma_a(min(q, nk - 1) * BK, q);
     __builtin_amdgcn_s_waitcnt(VM_FIRST);             // slab 0 landed (this thread's part)
     __builtin_amdgcn_s_barrier();                     // ... and every thread's
     __builtin_amdgcn_sched_barrier(0);
@@ -227,8 +231,13 @@ void gemm_nt_kernel(const T* __restrict__ A, const T* __restrict__ B,
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_barrier();
         __builtin_amdgcn_sched_barrier(0);
-        dma_a(min(kt + NS, nk - 1) * BK, kt % NS);
-        dma_b(min(kt + NB, nk - 1) * BK, kt % NB);
+        if constexpr (NA > NB) {
+          dma_b(min(kt + NB, nk - 1) * BK, kt % NB);
+          dma_a(min(kt + NA, nk - 1) * BK, kt % NA);
+        } else {
+          dma_a(min(kt + NA, nk - 1) * BK, kt % NA);
+          dma_b(min(kt + NB, nk - 1) * BK, kt % NB);
+        }
         nsl = min(kt + 1, nk - 1);
         nhs = 0;
       }
@@ -548,9 +557,10 @@ static const TileCfg kBf16Tiles[] = {
     {256, 128, 32, 128, 64, 3, 4, 2, "bf16_256x128x32_w128x64_swz3_lds2_pipe"},
     {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2_pipe_g4"},
     {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2b3_pipe_g4"},
+    {256, 256, 64, 128, 64, 1, 8, 2, "bf16_256x256x64_8w_w128x64_swz1_lds2a3_pipe_g4"},
 };
 
-int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 26; }
+int gemm_num_tiles(int dt) { return dt == DT_F32 ? 4 : 27; }
 const char* gemm_tile_name(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t].name : kBf16Tiles[t].name; }
 
 static const TileCfg& tile_cfg(int dt, int t) { return dt == DT_F32 ? kF32Tiles[t] : kBf16Tiles[t]; }
@@ -567,15 +577,15 @@ bool gemm_tile_ok(int dt, int t, const GemmShape& s, int epi) {
 }
 
 template <typename T, typename TO, int EPI, int BM, int BN, int BK, int WM, int WN, int SWZ, int NW = 4, int NS = 0,
-          int SCH = 0, int NSB = 0>
+          int SCH = 0, int NSB = 0, int NSA = 0>
 static hipError_t launch_t(const void* A, const void* B, void* C, const GemmShape& s, hipStream_t st,
                            const RopeEpi& rp, int gm = 8) {
   int tiles_m = (s.M + BM - 1) / BM, tiles_n = (s.N + BN - 1) / BN;
   const size_t ldk = BK + (SWZ == 0 ? 16 / sizeof(T) : 0);
-  size_t lds = NSB ? ((size_t)NS * BM + (size_t)NSB * BN) * ldk * sizeof(T)
-                   : (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * ldk * sizeof(T);
+  size_t lds = (NSA || NSB) ? ((size_t)(NSA ? NSA : NS) * BM + (size_t)(NSB ? NSB : NS) * BN) * ldk * sizeof(T)
+                           : (NS == 0 ? 2 : NS) * (size_t)(BM + BN) * ldk * sizeof(T);
   if (EPI == EPI_ROPE) lds = std::max(lds, (size_t)BM * (BN + 8) * 2);   // the staged BF16 tile
-  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, SCH, NSB>;
+  auto kern = gemm_nt_kernel<T, TO, BM, BN, BK, WM, WN, EPI, SWZ, NW, NS, SCH, NSB, NSA>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -624,7 +634,8 @@ static hipError_t launch_cfg(int tile, const void* A, const void* B, void* C, co
       case 22: return launch_t<T, TO, EPI, 128, 256, 32, 64, 128, 3, 4, 3, 1>(A, B, C, s, st, rp);
       case 23: return launch_t<T, TO, EPI, 256, 128, 32, 128, 64, 3, 4, 2, 1>(A, B, C, s, st, rp);
       case 24: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1>(A, B, C, s, st, rp, 4);
-      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1, 3>(A, B, C, s, st, rp, 4);
+      case 25: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1, 3>(A, B, C, s, st, rp, 4);
+      default: return launch_t<T, TO, EPI, 256, 256, 64, 128, 64, 1, 8, 2, 1, 0, 3>(A, B, C, s, st, rp, 4);
     }
   }
 }
