@@ -708,8 +708,8 @@ int gemm_pick_tile(int dt, int epi, const GemmShape& s) {
   if (dt == DT_F32) return s.M <= 64 ? 1 : 0;
   if (s.M <= 128) return 3;        // 64x128
   if (s.M < 8192) return 7;        // 128x128, 4 wavefronts
-  if (gemm_tile_ok(dt, 24, s, epi)) return 24;  // 256x256, 8 wavefronts of 128x64, direct loads, pipelined,
-                                                // groups of 4 M-tiles
+  if (gemm_tile_ok(dt, 26, s, epi)) return 26;  // 256x256, 8 wavefronts of 128x64, direct loads, pipelined,
+                                                // groups of 4 M-tiles, a third A-slab stage
   return 11;                       // 256x256, 8 wavefronts of 64x128
 }
 
